@@ -1,0 +1,181 @@
+/*
+ * libpic: MI355X (gfx950) hot path of one explicit, fully relativistic
+ * electromagnetic particle-in-cell step.
+ *
+ * The step follows the PIC loop of Fonseca et al., "Exploiting multi-scale
+ * parallelism for large scale numerical modelling of laser wakefield
+ * accelerators", Sec. 2 (deposit the current of the moving particles,
+ * advance E and B with the FDTD method, interpolate the fields at the
+ * particles, advance the fully relativistic equations of motion; time step
+ * under the Courant limit), in the per-particle order of its vector
+ * algorithm, Sec. 5.2 steps i-v (interpolation weights and field gather,
+ * equations of motion, virtual-particle trajectory splitting, charge-
+ * conserving deposit).  Positions are kept as an integer cell plus an
+ * offset normalised to the cell (Sec. 5.1), which makes single precision
+ * sufficient.
+ *
+ * Units: c = omega_p = 1; lengths in c/omega_p, time in 1/omega_p, momenta
+ * u = gamma*beta, fields in m c omega_p / e.  Maxwell: dB/dt = -curl E,
+ * dE/dt = curl B - J.  Macro-particle charges q_p are densities (q_p = -n/ppc
+ * for electrons at density n), so rho = sum q_p S and J = sum q_p v S.
+ *
+ * Conventions shared by every entry point:
+ *  - All array arguments are DEVICE pointers owned by the caller; the library
+ *    never allocates or frees caller memory.  Scratch lives in a caller-owned
+ *    device workspace of pic_workspace_bytes() bytes, zero-filled before its
+ *    first use, that must persist, and not be used by anything else, between
+ *    the calls on one context.
+ *  - "real" arrays hold float (real_bytes = 4) or double (real_bytes = 8).
+ *  - Grid arrays hold n0*n1*n2 reals per component, x fastest:
+ *    index = i + n0*(j + n1*k).  E_c and J_c sit at (i,j,k) + e_c/2, B_c at
+ *    (i,j,k) + (1,1,1)/2 - e_c/2 (the Yee layout; Sec. 5.1 notes that the
+ *    components sit at different positions), rho at the nodes (i,j,k).  In
+ *    2D (2D3V, d/dz = 0) n2 = 1 and all six components are kept.
+ *  - On an open axis of n nodes the domain is [0, n-1]: samples at
+ *    half-integer positions beyond node n-1 are outside and stay zero;
+ *    particles live in [0, n-1) and are absorbed when they leave it.
+ *  - Calls validate their arguments on the host and return a status code
+ *    synchronously; device work is only enqueued on `stream` (a hipStream_t,
+ *    NULL for the null stream).  Device-side anomalies (non-finite values,
+ *    offsets out of range) raise sticky flags read by pic_read_flags().
+ *  - A context must not be used from two host threads or two streams at once.
+ *    No C++ exception crosses this interface.
+ */
+#ifndef PIC_H
+#define PIC_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum pic_status {
+  PIC_OK = 0,
+  PIC_EINVAL = -1,   /* invalid argument (null pointer, size, order, dims) */
+  PIC_ECOURANT = -2, /* dt above the Courant limit 1/sqrt(sum 1/dx_d^2) */
+  PIC_EHIP = -3,     /* a HIP runtime call failed (no device, launch error) */
+  PIC_ESTATE = -4,   /* call order violated (e.g. push before any sort) */
+  PIC_EDEVICE = -5,  /* sticky device flags were raised (see pic_read_flags) */
+  PIC_ELDS = -6      /* tile geometry does not fit the 160 KB LDS of a CU */
+};
+
+enum pic_bc { PIC_BC_PERIODIC = 0, PIC_BC_OPEN = 1 };
+
+/* Sticky device flag bits. */
+enum pic_flag {
+  PIC_FLAG_NONFINITE = 1u << 0,  /* a momentum or gamma became NaN/Inf */
+  PIC_FLAG_OFFSET = 1u << 1,     /* an input offset was outside [0,1) */
+  PIC_FLAG_CELL = 1u << 2,       /* an input cell index was out of range */
+  PIC_FLAG_OVERSPEED = 1u << 3   /* a move exceeded one cell on some axis */
+};
+
+typedef struct pic_ctx pic_ctx; /* opaque, owned by the library */
+
+typedef struct {
+  int32_t dims;       /* 2 (2D3V) or 3 */
+  int32_t n[3];       /* nodes (= cells) per axis, n[2] = 1 in 2D; each >= 2 (>= 4 if open) */
+  double dx[3];       /* cell sizes, > 0 */
+  double dt;          /* time step, 0 < dt <= Courant limit */
+  int32_t order;      /* B-spline interpolation/deposit order, 1..3 */
+  int32_t real_bytes; /* 4 (FP32 offsets, momenta, fields) or 8 (FP64) */
+  int32_t bc[3];      /* pic_bc per axis (ignored for z in 2D) */
+  int32_t tile[3];    /* cells per tile per axis; 0 selects the default */
+  int32_t sort_every; /* pic_step re-sorts every this many steps (>= 1) */
+  int32_t drift;      /* cells a particle may drift out of its tile before it
+                         takes the global-memory path; < 0 selects the default */
+  double q_over_m;    /* charge-to-mass ratio (-1 for electrons) */
+  double q_const;     /* charge of every particle when pic_particles.q is NULL */
+} pic_config;
+
+typedef struct {
+  int64_t np;     /* particle slots in use (absorbed particles keep their slot) */
+  int32_t* cell;  /* linear index i+n0*(j+n1*k) of the cell's lower node; -1 = absorbed */
+  void* off[3];   /* real offsets in [0,1) from that node, in cell units (off[2] unused in 2D) */
+  void* u[3];     /* real momenta gamma*beta */
+  void* q;        /* real per-particle charge, or NULL to use q_const */
+  int32_t* id;    /* optional payload permuted with the particles by pic_sort, or NULL */
+} pic_particles;
+
+typedef struct {
+  void* E[3];
+  void* B[3];
+  void* J[3];
+} pic_fields;
+
+typedef struct {
+  double gauss_max;     /* max |(D.E - rho) - G_ref| over interior nodes */
+  double gauss_rel;     /* gauss_max / max |rho| */
+  double cont_max;      /* max |(rho - rho_prev)/dt + D.J| over interior nodes */
+  double cont_rel_l2;   /* ||C||_2 / ||(rho - rho_prev)/dt||_2 */
+  double cont_rel_inf;  /* cont_max / (max|rho| / dt) */
+  double w_field;       /* 1/2 sum (E^2 + B^2) dV over samples inside the domain */
+  double w_kin;         /* sum over live particles of |q_p| dV (gamma - 1) */
+  double rho_max;       /* max |rho| */
+  int64_t n_alive;      /* particles with cell >= 0 */
+  uint32_t flags;       /* sticky pic_flag bits */
+  int64_t n_slowpath;   /* particle pushes that took the global-memory path */
+} pic_diag;
+
+/* Validate `cfg` and create a context bound to the current HIP device.
+ * Returns PIC_EINVAL / PIC_ECOURANT / PIC_ELDS for a bad configuration
+ * (checked before any HIP call), PIC_EHIP if no device is usable.
+ * *out receives the context on success, NULL otherwise. */
+int pic_create(const pic_config* cfg, pic_ctx** out);
+
+/* Release the context (NULL is accepted). */
+int pic_destroy(pic_ctx* ctx);
+
+/* Bytes of device workspace needed for up to `np` particles. */
+int pic_workspace_bytes(const pic_ctx* ctx, int64_t np, size_t* bytes);
+
+/* Group the particles by tile (counting sort on the tile of `cell`, absorbed
+ * particles last), permuting every SoA array (and id) in place, and record
+ * the tile bins in `ws`.  Must precede pic_push_deposit.  This is the data
+ * layout change that makes the deposit local; it does not change physics. */
+int pic_sort(pic_ctx* ctx, pic_particles* p, void* ws, void* stream);
+
+/* One gather + Boris push + move + split + charge-conserving deposit pass
+ * over all live particles (Sec. 2 loop; Sec. 5.2 steps i-v): reads E^n, B^n
+ * at the particles, advances u^{n-1/2} -> u^{n+1/2} and x^n -> x^{n+1} in
+ * place, and overwrites f->J with J^{n+1/2}.  Requires a prior pic_sort with
+ * the same particle arrays and workspace (PIC_ESTATE otherwise). */
+int pic_push_deposit(pic_ctx* ctx, pic_particles* p, const pic_fields* f, void* ws,
+                     void* stream);
+
+/* FDTD (Yee) advance with J^{n+1/2}, in place: B -= dt/2 C E; E += dt (C^T B - J)
+ * with Mur first-order absorbing updates of the tangential E on open faces;
+ * B -= dt/2 C E (Sec. 2: FDTD method, local solver, Sec. 3). */
+int pic_field_advance(pic_ctx* ctx, pic_fields* f, void* ws, void* stream);
+
+/* `nsteps` full steps: pic_sort when due (every sort_every steps, counted
+ * per context, and before the first push), pic_push_deposit, pic_field_advance. */
+int pic_step(pic_ctx* ctx, pic_particles* p, pic_fields* f, int32_t nsteps, void* ws,
+             void* stream);
+
+/* FP64 charge density at the nodes from the stored cells and offsets with
+ * order-n node shapes; `rho` holds n0*n1*n2 doubles and is overwritten. */
+int pic_deposit_rho(pic_ctx* ctx, const pic_particles* p, double* rho, void* ws, void* stream);
+
+/* FP64 diagnostics (synchronises `stream`): deposits rho^n into `rho_out`,
+ * forms the Gauss residual D.E - rho^n (minus `gauss_ref` if not NULL; the
+ * residual field is written to `gauss_out` if not NULL) and, if `rho_prev`
+ * is not NULL, the continuity residual (rho^n - rho_prev)/dt + D.J with the
+ * J currently in `f`; reduces them with the energies into *out.  Interior
+ * nodes exclude 1 + order/2 node planes next to each open face. */
+int pic_diagnostics(pic_ctx* ctx, const pic_particles* p, const pic_fields* f,
+                    const double* rho_prev, const double* gauss_ref, double* rho_out,
+                    double* gauss_out, pic_diag* out, void* ws, void* stream);
+
+/* Read (and optionally clear) the sticky device flags and the slow-path
+ * counter (synchronises `stream`).  Returns PIC_EDEVICE if any flag is set. */
+int pic_read_flags(pic_ctx* ctx, void* ws, int clear, uint32_t* flags, int64_t* n_slowpath,
+                   void* stream);
+
+/* Human-readable name of a status code. */
+const char* pic_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

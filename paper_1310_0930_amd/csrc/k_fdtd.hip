@@ -1,0 +1,259 @@
+// FDTD (Yee) field advance: B -= dt/2 C E; E += dt (C^T B - J); B -= dt/2 C E.
+//
+// The paper advances the fields with the finite-difference time-domain method
+// (Sec. 2), a local, nearest-neighbour solver chosen for its small
+// communication volume (Sec. 3).  C is the forward-difference curl of E at
+// the B positions and C^T (its transpose) the backward-difference curl of B
+// at the E positions.  One thread per cell updates the three components;
+// reads of the neighbours along x are coalesced and the rest hit L2.
+//
+// Open faces: the tangential E samples on the first and last node planes of
+// an open axis are advanced with the first-order Mur condition
+// F0^{n+1} = F1^n + (dt - dx)/(dt + dx) (F1^{n+1} - F0^n), F1 the next sample
+// inward.  Samples on two open faces (edges) are done in a second pass along
+// the lower such axis.  Samples beyond the last node (half-integer positions)
+// are outside the domain, are never written and are read as zero.
+#include "k_common.h"
+
+namespace pic {
+
+struct FdParams {
+  int n[3];
+  int open[3];
+  int dims;
+  FastDiv dn0, dn1;
+};
+
+__device__ __forceinline__ void decompose(const FdParams& P, int idx, int& i, int& j, int& k) {
+  const uint32_t rest = P.dn0.div((uint32_t)idx);
+  i = idx - (int)rest * P.n[0];
+  if (P.dims == 3) {
+    const uint32_t r2 = P.dn1.div(rest);
+    j = (int)(rest - r2 * P.n[1]);
+    k = (int)r2;
+  } else {
+    j = (int)rest;
+    k = 0;
+  }
+}
+
+// Is the slot (i,j,k) of a component with staggering (sx,sy,sz) inside?
+__device__ __forceinline__ bool inside(const FdParams& P, int i, int j, int k, int sx, int sy, int sz) {
+  if (P.open[0] && i > P.n[0] - 1 - sx) return false;
+  if (P.open[1] && j > P.n[1] - 1 - sy) return false;
+  if (P.dims == 3 && P.open[2] && k > P.n[2] - 1 - sz) return false;
+  return true;
+}
+
+// Neighbour index along axis d (+1 or -1); -1 if it falls outside an open axis.
+__device__ __forceinline__ int nb(const FdParams& P, int i, int j, int k, int d, int step) {
+  int L[3] = {i, j, k};
+  L[d] += step;
+  if (L[d] < 0 || L[d] >= P.n[d]) {
+    if (P.open[d]) return -1;
+    L[d] = L[d] < 0 ? L[d] + P.n[d] : L[d] - P.n[d];
+  }
+  return L[0] + P.n[0] * (L[1] + P.n[1] * L[2]);
+}
+
+template <typename R>
+__device__ __forceinline__ R ld_or0(const R* a, int idx) {
+  return idx < 0 ? R(0) : a[idx];
+}
+
+// B -= h C E
+template <typename R>
+__global__ void k_half_b(FdParams P, const R* __restrict__ E0, const R* __restrict__ E1,
+                         const R* __restrict__ E2, R* __restrict__ B0, R* __restrict__ B1,
+                         R* __restrict__ B2, R hx, R hy, R hz, int ncell) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= ncell) return;
+  int i, j, k;
+  decompose(P, idx, i, j, k);
+  const R* E[3] = {E0, E1, E2};
+  R* B[3] = {B0, B1, B2};
+  const R h[3] = {hx, hy, hz};  // dt/2 / dx_d
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    if (!inside(P, i, j, k, c != 0, c != 1, c != 2)) continue;
+    const int a = (c + 1) % 3, b = (c + 2) % 3;
+    R acc = R(0);
+    // + d_a E_b - d_b E_a, forward differences
+    if (a < P.dims) acc += h[a] * (ld_or0(E[b], nb(P, i, j, k, a, 1)) - E[b][idx]);
+    if (b < P.dims) acc -= h[b] * (ld_or0(E[a], nb(P, i, j, k, b, 1)) - E[a][idx]);
+    B[c][idx] -= acc;
+  }
+}
+
+// Tangential E on the boundary plane of an open axis d != c?  Returns the
+// number of such axes and the lowest one.
+__device__ __forceinline__ int mur_axes(const FdParams& P, int c, int i, int j, int k, int& lowest) {
+  const int L[3] = {i, j, k};
+  int cnt = 0;
+  lowest = -1;
+  for (int d = 0; d < P.dims; ++d) {
+    if (d == c || !P.open[d]) continue;
+    if (L[d] == 0 || L[d] == P.n[d] - 1) {
+      if (cnt == 0) lowest = d;
+      ++cnt;
+    }
+  }
+  return cnt;
+}
+
+// Offset of the saved plane (axis d, side s, component c) in the Mur buffer
+// and the index of (i,j,k) inside it.
+struct MurPlanes {
+  long off[3][2][3];
+  int na[3], nbb[3];  // the two other axes per d (a < b)
+};
+
+// E += dt (C^T B - J) on interior samples; saves E^n next to open faces.
+template <typename R>
+__global__ void k_advance_e(FdParams P, MurPlanes M, R* __restrict__ E0, R* __restrict__ E1,
+                            R* __restrict__ E2, const R* __restrict__ B0, const R* __restrict__ B1,
+                            const R* __restrict__ B2, const R* __restrict__ J0,
+                            const R* __restrict__ J1, const R* __restrict__ J2, R gx, R gy, R gz,
+                            R dt, int ncell, R* __restrict__ save) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= ncell) return;
+  int i, j, k;
+  decompose(P, idx, i, j, k);
+  R* E[3] = {E0, E1, E2};
+  const R* B[3] = {B0, B1, B2};
+  const R* J[3] = {J0, J1, J2};
+  const R g[3] = {gx, gy, gz};  // dt / dx_d
+  const int L[3] = {i, j, k};
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    if (!inside(P, i, j, k, c == 0, c == 1, c == 2)) continue;
+    // keep E^n of samples next to an open face for the Mur update
+    for (int d = 0; d < P.dims; ++d) {
+      if (d == c || !P.open[d]) continue;
+      const int side = L[d] == 1 ? 0 : (L[d] == P.n[d] - 2 ? 1 : -1);
+      if (side < 0) continue;
+      const int a = d == 0 ? 1 : 0, b = d == 2 ? 1 : 2;
+      const long pos = M.off[d][side][c] + L[a] + (long)M.na[d] * (b < 3 ? L[b] : 0);
+      save[pos] = E[c][idx];
+    }
+    int lowest;
+    if (mur_axes(P, c, i, j, k, lowest) > 0) continue;
+    const int a = (c + 1) % 3, b = (c + 2) % 3;
+    R curl = R(0);
+    // + d_a B_b - d_b B_a, backward differences
+    if (a < P.dims) curl += g[a] * (B[b][idx] - ld_or0(B[b], nb(P, i, j, k, a, -1)));
+    if (b < P.dims) curl -= g[b] * (B[a][idx] - ld_or0(B[a], nb(P, i, j, k, b, -1)));
+    E[c][idx] += curl - dt * J[c][idx];
+  }
+}
+
+// Mur update of the samples on the face (d, side) with exactly `pass` open
+// boundary axes, along their lowest such axis.
+template <typename R>
+__global__ void k_mur(FdParams P, MurPlanes M, R* __restrict__ E0, R* __restrict__ E1,
+                      R* __restrict__ E2, int d, int side, int pass, R kappa,
+                      const R* __restrict__ save) {
+  const int a = d == 0 ? 1 : 0, b = d == 2 ? 1 : 2;
+  const int na = P.n[a], nbv = b < P.dims ? P.n[b] : 1;
+  const long plane = (long)na * nbv;
+  const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (t >= 2 * plane) return;
+  const int which = (int)(t / plane);
+  const long r = t - which * plane;
+  const int c = (d + 1 + which) % 3;  // the two components tangential to the face
+  int L[3];
+  L[d] = side ? P.n[d] - 1 : 0;
+  L[a] = (int)(r % na);
+  L[b] = (int)(r / na);
+  if (P.dims == 2 && b == 2 && L[b] != 0) return;
+  if (!inside(P, L[0], L[1], L[2], c == 0, c == 1, c == 2)) return;
+  int lowest;
+  if (mur_axes(P, c, L[0], L[1], L[2], lowest) != pass || lowest != d) return;
+  R* E[3] = {E0, E1, E2};
+  const int i0 = L[0] + P.n[0] * (L[1] + P.n[1] * L[2]);
+  int N[3] = {L[0], L[1], L[2]};
+  N[d] += side ? -1 : 1;
+  const int i1 = N[0] + P.n[0] * (N[1] + P.n[1] * N[2]);
+  const R f1_old = save[M.off[d][side][c] + L[a] + (long)M.na[d] * L[b]];
+  E[c][i0] = f1_old + kappa * (E[c][i1] - E[c][i0]);
+}
+
+template <typename R>
+static int launch_fa(const pic_ctx* ctx, const pic_fields* f, void* ws, hipStream_t s) {
+  const pic_config& cf = ctx->cfg;
+  FdParams P;
+  P.dims = cf.dims;
+  for (int d = 0; d < 3; ++d) {
+    P.n[d] = d < cf.dims ? cf.n[d] : 1;
+    P.open[d] = d < cf.dims && cf.bc[d] == PIC_BC_OPEN;
+  }
+  P.dn0.init((uint32_t)P.n[0]);
+  P.dn1.init((uint32_t)P.n[1]);
+  const int ncell = P.n[0] * P.n[1] * P.n[2];
+  const R dt = (R)cf.dt;
+  R h[3], g[3];
+  for (int d = 0; d < 3; ++d) {
+    h[d] = (R)(0.5 * cf.dt / cf.dx[d]);
+    g[d] = (R)(cf.dt / cf.dx[d]);
+  }
+  R* E[3];
+  R* B[3];
+  R* J[3];
+  for (int c = 0; c < 3; ++c) {
+    E[c] = (R*)f->E[c];
+    B[c] = (R*)f->B[c];
+    J[c] = (R*)f->J[c];
+  }
+  WsLayout L = ws_layout(ctx, 0);
+  R* save = (R*)((char*)ws + L.mur);
+  MurPlanes M;
+  long off = 0;
+  for (int d = 0; d < 3; ++d) {
+    const int a = d == 0 ? 1 : 0, b = d == 2 ? 1 : 2;
+    M.na[d] = P.n[a];
+    M.nbb[d] = P.n[b];
+    for (int sd = 0; sd < 2; ++sd)
+      for (int c = 0; c < 3; ++c) {
+        M.off[d][sd][c] = off;
+        if (P.open[d] && c != d) off += (long)P.n[a] * P.n[b];
+      }
+  }
+  const unsigned grid = (unsigned)((ncell + 255) / 256);
+  k_half_b<R><<<dim3(grid), dim3(256), 0, s>>>(P, E[0], E[1], E[2], B[0], B[1], B[2], h[0], h[1],
+                                              h[2], ncell);
+  k_advance_e<R><<<dim3(grid), dim3(256), 0, s>>>(P, M, E[0], E[1], E[2], B[0], B[1], B[2], J[0],
+                                                 J[1], J[2], g[0], g[1], g[2], dt, ncell, save);
+  for (int pass = 1; pass <= 2; ++pass)
+    for (int d = 0; d < cf.dims; ++d) {
+      if (!P.open[d]) continue;
+      const int a = d == 0 ? 1 : 0, b = d == 2 ? 1 : 2;
+      const long plane = (long)P.n[a] * P.n[b];
+      const R kappa = (R)((cf.dt - cf.dx[d]) / (cf.dt + cf.dx[d]));
+      for (int sd = 0; sd < 2; ++sd)
+        k_mur<R><<<dim3((unsigned)((2 * plane + 255) / 256)), dim3(256), 0, s>>>(
+            P, M, E[0], E[1], E[2], d, sd, pass, kappa, save);
+    }
+  k_half_b<R><<<dim3(grid), dim3(256), 0, s>>>(P, E[0], E[1], E[2], B[0], B[1], B[2], h[0], h[1],
+                                              h[2], ncell);
+  return (int)hipGetLastError();
+}
+
+int launch_field_advance(const pic_ctx* ctx, const pic_fields* f, void* ws, hipStream_t s) {
+  return ctx->cfg.real_bytes == 8 ? launch_fa<double>(ctx, f, ws, s)
+                                  : launch_fa<float>(ctx, f, ws, s);
+}
+
+// Size (in reals) of the Mur save buffer.
+long mur_len(const pic_config& cf) {
+  long len = 0;
+  int n[3];
+  for (int d = 0; d < 3; ++d) n[d] = d < cf.dims ? cf.n[d] : 1;
+  for (int d = 0; d < cf.dims; ++d) {
+    if (cf.bc[d] != PIC_BC_OPEN) continue;
+    const int a = d == 0 ? 1 : 0, b = d == 2 ? 1 : 2;
+    len += 2L * 2L * n[a] * n[b];
+  }
+  return len;
+}
+
+}  // namespace pic

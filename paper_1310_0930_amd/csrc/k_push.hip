@@ -1,0 +1,652 @@
+// Fused gather + relativistic Boris push + move + trajectory split +
+// charge-conserving (Esirkepov) deposit, one workgroup per tile.
+//
+// This is the per-particle body of the PIC loop (Sec. 2) in the order of the
+// paper's vector algorithm (Sec. 5.2, steps i-v).  The paper vectorises it
+// over 4/8 SIMD lanes, emulates the field gather with serial loads and
+// shuffles, and avoids write conflicts with a serial scatter of the virtual
+// particles (or per-thread copies of the current grid, Sec. 3.1).  Here each
+// 64-wide wavefront lane owns a particle; the workgroup stages the E and B
+// samples of its tile (plus halo) in LDS once, so the gather is a set of
+// LDS reads at compile-time offsets, and accumulates the current of every
+// virtual segment into an LDS tile with LDS float atomics before one
+// coalesced flush with global atomics where tile halos overlap.
+//
+// Positions are an integer cell plus an offset in [0,1) normalised to the
+// cell (Sec. 5.1); all shape arguments are formed from the stored offsets
+// without rounding, and the shape differences of the deposit are formed in
+// factored form, so that single precision keeps charge conservation at the
+// level of the stored positions.
+#include "k_common.h"
+
+namespace pic {
+
+// ------------------------------------------------------------------ shapes
+// Piece of the order-n B-spline that holds a node-centred position c + o
+// (o in [0,1)), relative to c, and the coordinate xi inside that piece
+// (xi in [0,1) for odd orders, [-1/2,1/2) for even orders).  Exact.
+template <int ORDER, typename R>
+__device__ __forceinline__ int piece_node(R o, R& xi) {
+  if (ORDER & 1) {
+    xi = o;
+    return 0;
+  }
+  const int k = o >= R(0.5);
+  xi = k ? o - R(1) : o;
+  return k;
+}
+
+// The same for a position half a cell lower (a component staggered along
+// the axis): P = o - 1/2.
+template <int ORDER, typename R>
+__device__ __forceinline__ int piece_stag(R o, R& xi) {
+  if (ORDER & 1) {
+    const int k = o >= R(0.5) ? 0 : -1;
+    xi = k ? o + R(0.5) : o - R(0.5);
+    return k;
+  }
+  xi = o - R(0.5);
+  return 0;
+}
+
+// B-spline weights of the piece at coordinate xi, on nodes base..base+ORDER
+// where base = piece - ORDER/2.
+template <int ORDER, typename R>
+__device__ __forceinline__ void shape(R xi, R* w) {
+  if (ORDER == 1) {
+    w[0] = R(1) - xi;
+    w[1] = xi;
+  } else if (ORDER == 2) {
+    const R a = R(0.5) - xi, b = R(0.5) + xi;
+    w[0] = R(0.5) * a * a;
+    w[1] = R(0.75) - xi * xi;
+    w[2] = R(0.5) * b * b;
+  } else {
+    const R s = R(1) - xi, t2 = xi * xi, t3 = t2 * xi;
+    const R sixth = R(1.0 / 6.0);
+    w[0] = sixth * s * s * s;
+    w[1] = sixth * (R(4) - R(6) * t2 + R(3) * t3);
+    w[2] = sixth * (R(1) + R(3) * xi + R(3) * t2 - R(3) * t3);
+    w[3] = sixth * t3;
+  }
+}
+
+// Shape differences S(xb) - S(xa) on one piece, in factored form
+// (xb - xa) * g(xa, xb): the difference of the end points is formed once,
+// so a short move does not lose its digits to cancellation.
+template <int ORDER, typename R>
+__device__ __forceinline__ void dshape(R xa, R xb, R* d) {
+  const R dl = xb - xa;
+  if (ORDER == 1) {
+    d[0] = -dl;
+    d[1] = dl;
+  } else if (ORDER == 2) {
+    const R s = xa + xb;
+    d[0] = R(-0.5) * dl * (R(1) - s);
+    d[1] = -dl * s;
+    d[2] = R(0.5) * dl * (R(1) + s);
+  } else {
+    const R sixth = R(1.0 / 6.0);
+    const R s = xa + xb;
+    const R Q = xa * xa + xa * xb + xb * xb;
+    const R aa = R(1) - xa, ab = R(1) - xb;
+    d[0] = -sixth * dl * (aa * aa + aa * ab + ab * ab);
+    d[1] = sixth * dl * (R(-6) * s + R(3) * Q);
+    d[2] = sixth * dl * (R(3) + R(3) * s - R(3) * Q);
+    d[3] = sixth * dl * Q;
+  }
+}
+
+// ------------------------------------------------------------------ accessors
+// E/B samples staged in LDS: comp 0..2 = E, 3..5 = B.  `base` is the
+// particle's cell in region coordinates; ref() folds a component's first
+// stencil node into one index so that every stencil offset below is a
+// compile-time immediate of the LDS read.
+template <int DIMS, int ORDER, typename R>
+struct LdsFields {
+  using G = Geo<DIMS, ORDER, R>;
+  const R* s;
+  int base;
+  __device__ __forceinline__ const R* ref(int comp, const int* b) const {
+    return s + comp * G::e_vol + base + (b[2] * G::ex + b[1]) * G::ex + b[0];
+  }
+  __device__ __forceinline__ R at(const R* r, int /*comp*/, int i, int j, int k) const {
+    return r[(k * G::ex + j) * G::ex + i];
+  }
+};
+
+// E/B straight from global memory, with periodic wrap and zero outside the
+// domain of open axes (the path of particles that drifted off their tile).
+template <typename R>
+struct GlobalFields {
+  const R* const* E;
+  const R* const* B;
+  int cx, cy, cz;
+  int n0, n1, n2;
+  int o0, o1, o2;  // open flags
+  int dims;
+  struct Ref {
+    int x, y, z;
+  };
+  __device__ __forceinline__ Ref ref(int /*comp*/, const int* b) const {
+    return {cx + b[0], cy + b[1], cz + b[2]};
+  }
+  __device__ __forceinline__ R at(const Ref& r, int comp, int i, int j, int k) const {
+    const int c = comp < 3 ? comp : comp - 3;
+    const bool isb = comp >= 3;
+    const int sx = isb ? (c != 0) : (c == 0);
+    const int sy = isb ? (c != 1) : (c == 1);
+    const int sz = isb ? (c != 2) : (c == 2);
+    const int ix = axis_slot(r.x + i, n0, o0, sx);
+    const int iy = axis_slot(r.y + j, n1, o1, sy);
+    const int iz = dims == 3 ? axis_slot(r.z + k, n2, o2, sz) : 0;
+    if (ix < 0 || iy < 0 || iz < 0) return R(0);
+    const R* f = isb ? B[c] : E[c];
+    return f[ix + n0 * (iy + n1 * iz)];
+  }
+};
+
+// Current sinks.  segment() fixes the first stencil node of a virtual
+// segment; add() then takes compile-time offsets from it.  The LDS tile
+// accumulates in double (see Geo); the global sink is the path of
+// particles off their tile.
+template <int DIMS, int ORDER, typename R>
+struct LdsCurrent {
+  using G = Geo<DIMS, ORDER, R>;
+  double* s;
+  int base;  // the particle's old cell in the J region
+  double* seg;
+  __device__ __forceinline__ void segment(const int* b) {
+    seg = s + base + (b[2] * G::jx + b[1]) * G::jx + b[0];
+  }
+  __device__ __forceinline__ void add(int comp, int i, int j, int k, R v) const {
+    atomicAdd(&seg[comp * G::j_vol + (k * G::jx + j) * G::jx + i], (double)v);
+  }
+};
+
+template <typename R>
+struct GlobalCurrent {
+  R* const* J;
+  int cx, cy, cz;
+  int n0, n1, n2;
+  int o0, o1, o2;
+  int dims;
+  int sx, sy, sz;
+  __device__ __forceinline__ void segment(const int* b) {
+    sx = cx + b[0];
+    sy = cy + b[1];
+    sz = cz + b[2];
+  }
+  __device__ __forceinline__ void add(int comp, int i, int j, int k, R v) const {
+    const int ix = axis_slot(sx + i, n0, o0, comp == 0);
+    const int iy = axis_slot(sy + j, n1, o1, comp == 1);
+    const int iz = dims == 3 ? axis_slot(sz + k, n2, o2, comp == 2) : 0;
+    if (ix < 0 || iy < 0 || iz < 0) return;  // dropped beyond an open face
+    atomic_add(&J[comp][ix + n0 * (iy + n1 * iz)], v);
+  }
+};
+
+// ------------------------------------------------------------------ gather
+// Order-n interpolation of one component: weights per axis `w`, first node
+// offsets `b` relative to the particle's cell.
+template <int DIMS, int ORDER, typename R, class Acc>
+__device__ __forceinline__ R interp(const Acc& acc, int comp, const R (*w)[ORDER + 1],
+                                    const int* b) {
+  constexpr int M = ORDER + 1;
+  constexpr int MZ = DIMS == 3 ? M : 1;
+  const auto r = acc.ref(comp, b);
+  R s = R(0);
+#pragma unroll
+  for (int k = 0; k < MZ; ++k) {
+    R sy = R(0);
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      R sx = R(0);
+#pragma unroll
+      for (int i = 0; i < M; ++i) sx += w[0][i] * acc.at(r, comp, i, j, k);
+      sy += w[1][j] * sx;
+    }
+    s += (DIMS == 3 ? w[2][k] : R(1)) * sy;
+  }
+  return s;
+}
+
+// E and B at the particle (Sec. 5.2 steps i-ii): each component with the
+// weights of its own Yee position, staggered along its axis (E_c) or along
+// the two other axes (B_c).
+template <int DIMS, int ORDER, typename R, class Acc>
+__device__ __forceinline__ void gather(const Acc& acc, const R* o, R* Ep, R* Bp) {
+  constexpr int M = ORDER + 1;
+  R wn[3][M], ws[3][M];
+  int bn[3] = {0, 0, 0}, bs[3] = {0, 0, 0};
+#pragma unroll
+  for (int d = 0; d < DIMS; ++d) {
+    R xi;
+    bn[d] = piece_node<ORDER>(o[d], xi) - ORDER / 2;
+    shape<ORDER>(xi, wn[d]);
+    bs[d] = piece_stag<ORDER>(o[d], xi) - ORDER / 2;
+    shape<ORDER>(xi, ws[d]);
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    R we[3][M], wb[3][M];
+    int be[3], bb[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const bool se = (d == c), sb = (d != c);
+#pragma unroll
+      for (int i = 0; i < M; ++i) {
+        we[d][i] = se ? ws[d][i] : wn[d][i];
+        wb[d][i] = sb ? ws[d][i] : wn[d][i];
+      }
+      be[d] = se ? bs[d] : bn[d];
+      bb[d] = sb ? bs[d] : bn[d];
+    }
+    Ep[c] = interp<DIMS, ORDER, R>(acc, c, we, be);
+    Bp[c] = interp<DIMS, ORDER, R>(acc, 3 + c, wb, bb);
+  }
+}
+
+// ------------------------------------------------------------------ push
+// Relativistic Boris step (Sec. 5.2 step iii; Boris is this build's reading
+// of "fully relativistic equations of motion"): half electric kick, magnetic
+// rotation with gamma of the half-kicked momentum, half electric kick.
+template <typename R>
+__device__ __forceinline__ void boris(R hqm, R* u, const R* E, const R* B) {
+  R um[3], t[3], s[3], up[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) um[c] = u[c] + hqm * E[c];
+  const R gm = sqrt(R(1) + um[0] * um[0] + um[1] * um[1] + um[2] * um[2]);
+  const R hg = hqm / gm;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) t[c] = hg * B[c];
+  const R f = R(2) / (R(1) + t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) s[c] = f * t[c];
+  up[0] = um[0] + (um[1] * t[2] - um[2] * t[1]);
+  up[1] = um[1] + (um[2] * t[0] - um[0] * t[2]);
+  up[2] = um[2] + (um[0] * t[1] - um[1] * t[0]);
+  u[0] = um[0] + (up[1] * s[2] - up[2] * s[1]) + hqm * E[0];
+  u[1] = um[1] + (up[2] * s[0] - up[0] * s[2]) + hqm * E[1];
+  u[2] = um[2] + (up[0] * s[1] - up[1] * s[0]) + hqm * E[2];
+}
+
+// ------------------------------------------------------------------ deposit
+// Charge-conserving current of the straight path from offset o0 in the old
+// cell to offset o1 in the cell shifted by sh (Sec. 5.2 steps iv-v): split
+// at the planes where the node stencil switches (one per axis at most; at
+// most DIMS+1 virtual segments), then the Esirkepov density decomposition
+// on each segment's own (n+1)^D stencil.  J_c at the slots base_c + i
+// (i < n) is fac_c * P_c[i] * A_c(j,k), where P_c is the running sum of the
+// shape differences along c and A_c the time-averaged transverse weight.
+// Every segment end is expressed in the piece frame of its stencil: crossing
+// points exactly on their plane, other coordinates once per point.
+template <int DIMS, int ORDER, typename R, class Sink>
+__device__ __forceinline__ void deposit(Sink sink, const R* jfac, const R* o0,
+                                        const int* sh, const R* o1, R q, R vz) {
+  constexpr int M = ORDER + 1;
+  constexpr bool odd = ORDER & 1;
+  int k0[3], k1[3];
+  R xi0[3], xi1[3], dl[3], pk0[3], pk1[3], fr[3];
+  bool cr[3];
+#pragma unroll
+  for (int d = 0; d < DIMS; ++d) {
+    k0[d] = piece_node<ORDER>(o0[d], xi0[d]);
+    k1[d] = sh[d] + piece_node<ORDER>(o1[d], xi1[d]);
+    dl[d] = R(k1[d] - k0[d]) + (xi1[d] - xi0[d]);
+    cr[d] = false;
+    fr[d] = R(2);
+    pk0[d] = pk1[d] = R(0);
+    if (k1[d] != k0[d]) {
+      const bool up = k1[d] > k0[d];
+      pk0[d] = odd ? (up ? R(1) : R(0)) : (up ? R(0.5) : R(-0.5));
+      pk1[d] = odd ? (up ? R(0) : R(1)) : (up ? R(-0.5) : R(0.5));
+      const R f = (pk0[d] - xi0[d]) / dl[d];
+      if (f > R(0) && f < R(1)) {
+        cr[d] = true;
+        fr[d] = f;
+      } else if (!(f > R(0))) {  // starts on the plane: the path is in piece k1
+        k0[d] = k1[d];
+        xi0[d] = pk1[d];
+      } else {  // ends on the plane: the path is in piece k0
+        k1[d] = k0[d];
+        xi1[d] = pk0[d];
+      }
+    }
+  }
+  // ascending crossing fractions; jd[d] = index of axis d's crossing point
+  R tb[DIMS + 2];
+  int jd[3] = {DIMS + 2, DIMS + 2, DIMS + 2};
+  int m = 0;
+  tb[0] = R(0);
+#pragma unroll
+  for (int d = 0; d < DIMS; ++d) {
+    if (!cr[d]) continue;
+    int rank = 1;
+#pragma unroll
+    for (int e = 0; e < DIMS; ++e)
+      if (e != d && cr[e] && (fr[e] < fr[d] || (fr[e] == fr[d] && e < d))) ++rank;
+    jd[d] = rank;
+    ++m;
+  }
+#pragma unroll
+  for (int d = 0; d < DIMS; ++d)
+    if (cr[d]) tb[jd[d]] = fr[d];
+  tb[m + 1] = R(1);
+
+  for (int s = 0; s <= m; ++s) {
+    // mean weight Sm = S0 + dS/2 and dS/12: the Esirkepov transverse factor
+    // S0a S0b + (dSa S0b + S0a dSb)/2 + dSa dSb/3 equals Sma Smb + dSa dSb/12
+    R Sm[3][M], dS[3][M], d12[3][M];
+    int base[3] = {0, 0, 0};
+#pragma unroll
+    for (int d = 0; d < DIMS; ++d) {
+      const bool f1 = cr[d] && s >= jd[d];
+      R xa, xb;
+      if (s == 0)
+        xa = xi0[d];
+      else if (cr[d] && s == jd[d])
+        xa = pk1[d];
+      else
+        xa = f1 ? xi1[d] - (R(1) - tb[s]) * dl[d] : xi0[d] + tb[s] * dl[d];
+      if (s == m)
+        xb = xi1[d];
+      else if (cr[d] && s + 1 == jd[d])
+        xb = pk0[d];
+      else
+        xb = f1 ? xi1[d] - (R(1) - tb[s + 1]) * dl[d] : xi0[d] + tb[s + 1] * dl[d];
+      base[d] = (f1 ? k1[d] : k0[d]) - ORDER / 2;
+      R S0[M];
+      shape<ORDER>(xa, S0);
+      dshape<ORDER>(xa, xb, dS[d]);
+#pragma unroll
+      for (int i = 0; i < M; ++i) {
+        Sm[d][i] = S0[i] + R(0.5) * dS[d][i];
+        d12[d][i] = R(1.0 / 12.0) * dS[d][i];
+      }
+    }
+    Sink sk = sink;
+    sk.segment(base);
+    if (DIMS == 3) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const int a = (c + 1) % 3, b = (c + 2) % 3;
+        R P[ORDER];
+        R run = R(0);
+#pragma unroll
+        for (int i = 0; i < ORDER; ++i) {
+          run += dS[c][i];
+          P[i] = q * jfac[c] * run;
+        }
+#pragma unroll
+        for (int ib = 0; ib < M; ++ib)
+#pragma unroll
+          for (int ia = 0; ia < M; ++ia) {
+            const R A = Sm[a][ia] * Sm[b][ib] + d12[a][ia] * dS[b][ib];
+#pragma unroll
+            for (int ic = 0; ic < ORDER; ++ic) {
+              int L[3];
+              L[c] = ic;
+              L[a] = ia;
+              L[b] = ib;
+              sk.add(c, L[0], L[1], L[2], P[ic] * A);
+            }
+          }
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const int a = 1 - c;
+        R P[ORDER];
+        R run = R(0);
+#pragma unroll
+        for (int i = 0; i < ORDER; ++i) {
+          run += dS[c][i];
+          P[i] = q * jfac[c] * run;
+        }
+#pragma unroll
+        for (int ia = 0; ia < M; ++ia) {
+#pragma unroll
+          for (int ic = 0; ic < ORDER; ++ic) {
+            int L[2];
+            L[c] = ic;
+            L[a] = ia;
+            sk.add(c, L[0], L[1], 0, P[ic] * Sm[a][ia]);
+          }
+        }
+      }
+      const R fz = q * vz * (tb[s + 1] - tb[s]);
+#pragma unroll
+      for (int j = 0; j < M; ++j)
+#pragma unroll
+        for (int i = 0; i < M; ++i)
+          sk.add(2, i, j, 0, fz * (Sm[0][i] * Sm[1][j] + d12[0][i] * dS[1][j]));
+    }
+  }
+}
+
+// ------------------------------------------------------------------ kernel
+template <int DIMS, int ORDER, typename R>
+__global__ void __launch_bounds__((Geo<DIMS, ORDER, R>::NT)) k_push_deposit(
+    KParams<R> P, DParts<R> pa, DFields<R> F, const int* __restrict__ starts, DevFlags* flg) {
+  using G = Geo<DIMS, ORDER, R>;
+  __shared__ R s_eb[6 * G::e_vol];
+  __shared__ double s_j[3 * G::j_vol];
+
+  // XCD-aware remap: consecutive block ids go round-robin over the 8 XCDs,
+  // so give each XCD a contiguous range of tiles (neighbouring tiles share
+  // halo samples in that XCD's L2).
+  const int tile = (blockIdx.x & 7) * P.per_xcd + (blockIdx.x >> 3);
+  if (tile >= P.ntiles) return;
+  const int pbeg = starts[tile], pend = starts[tile + 1];
+  if (pbeg == pend) return;
+  const int tx = tile % P.ntile[0];
+  const int ty = (tile / P.ntile[0]) % P.ntile[1];
+  const int tz = tile / (P.ntile[0] * P.ntile[1]);
+  const int ox = tx * G::T, oy = ty * G::T, oz = tz * G::TZ;
+  const int open0 = P.bc[0] == PIC_BC_OPEN, open1 = P.bc[1] == PIC_BC_OPEN;
+  const int open2 = DIMS == 3 && P.bc[2] == PIC_BC_OPEN;
+
+  // stage E and B of tile + halo (zero outside open faces)
+  for (int idx = threadIdx.x; idx < 6 * G::e_vol; idx += G::NT) {
+    const int comp = idx / G::e_vol;
+    const int r = idx - comp * G::e_vol;
+    const int lx = r % G::ex, ly = (r / G::ex) % G::ex, lz = r / (G::ex * G::ex);
+    const int c = comp < 3 ? comp : comp - 3;
+    const bool isb = comp >= 3;
+    const int ix = axis_slot(ox + G::e_lo + lx, P.n[0], open0, isb ? (c != 0) : (c == 0));
+    const int iy = axis_slot(oy + G::e_lo + ly, P.n[1], open1, isb ? (c != 1) : (c == 1));
+    const int iz = DIMS == 3 ? axis_slot(oz + G::e_lo_z + lz, P.n[2], open2, isb ? (c != 2) : (c == 2))
+                             : 0;
+    R v = R(0);
+    if (ix >= 0 && iy >= 0 && iz >= 0) {
+      const R* f = isb ? F.B[c] : F.E[c];
+      v = f[ix + P.n[0] * (iy + P.n[1] * iz)];
+    }
+    s_eb[idx] = v;
+  }
+  for (int idx = threadIdx.x; idx < 3 * G::j_vol; idx += G::NT) s_j[idx] = 0.0;
+  __syncthreads();
+
+  const int ncell = P.n[0] * P.n[1] * P.n[2];
+  for (int p = pbeg + threadIdx.x; p < pend; p += G::NT) {
+    const int cl = pa.cell[p];
+    if (cl < 0) continue;  // absorbed
+    R o[3] = {R(0), R(0), R(0)}, u[3];
+#pragma unroll
+    for (int d = 0; d < DIMS; ++d) o[d] = pa.off[d][p];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) u[c] = pa.u[c][p];
+    const R q = pa.q ? pa.q[p] : P.q_const;
+    bool bad = cl >= ncell;
+#pragma unroll
+    for (int d = 0; d < DIMS; ++d) bad |= !(o[d] >= R(0) && o[d] < R(1));
+    if (bad) {  // keeps every index below in bounds
+      raise_flag(flg, cl >= ncell ? PIC_FLAG_CELL : PIC_FLAG_OFFSET);
+      continue;
+    }
+    const uint32_t rest = P.dn0.div((uint32_t)cl);
+    int c3[3];
+    c3[0] = cl - (int)rest * P.n[0];
+    c3[1] = DIMS == 3 ? (int)(rest - P.dn1.div(rest) * P.n[1]) : (int)rest;
+    c3[2] = DIMS == 3 ? (int)P.dn1.div(rest) : 0;
+    // position relative to the tile origin (periodic image inside the window)
+    int l[3];
+    bool fast = true;
+    const int org[3] = {ox, oy, oz};
+#pragma unroll
+    for (int d = 0; d < DIMS; ++d) {
+      const int Td = d == 2 ? G::TZ : G::T;
+      const int Ad = d == 2 ? G::AZ : G::A;
+      int v = c3[d] - org[d];
+      if (P.bc[d] == PIC_BC_PERIODIC) {
+        v = v < 0 ? v + P.n[d] : v;
+        if (v >= Td + Ad) v -= P.n[d];
+      }
+      l[d] = v;
+      fast = fast && v >= -Ad && v < Td + Ad;
+    }
+    if (DIMS == 2) l[2] = 0;
+
+    R Ep[3], Bp[3];
+    if (fast) {
+      LdsFields<DIMS, ORDER, R> acc{
+          s_eb, ((l[2] - G::e_lo_z) * G::ex + (l[1] - G::e_lo)) * G::ex + (l[0] - G::e_lo)};
+      gather<DIMS, ORDER, R>(acc, o, Ep, Bp);
+    } else {
+      GlobalFields<R> acc{F.E, F.B, c3[0], c3[1], c3[2], P.n[0], P.n[1], P.n[2],
+                          open0, open1, open2, DIMS};
+      gather<DIMS, ORDER, R>(acc, o, Ep, Bp);
+    }
+    boris<R>(P.hqm, u, Ep, Bp);
+    const R gam = sqrt(R(1) + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    if (!isfinite(gam)) {
+      raise_flag(flg, PIC_FLAG_NONFINITE);
+      pa.cell[p] = -1;
+      continue;
+    }
+    const R ig = R(1) / gam;
+    // move in cell units; the new offset and cell shift are exact functions
+    // of the rounded sum, and the deposit uses exactly the stored result
+    int sh[3] = {0, 0, 0};
+    R o1[3] = {R(0), R(0), R(0)};
+    bool small = true, absorbed = false;
+    int c1[3] = {c3[0], c3[1], c3[2]};
+#pragma unroll
+    for (int d = 0; d < DIMS; ++d) {
+      const R dlt = u[d] * ig * P.dtdx[d];
+      // |move| < 0.49 keeps every segment stencil inside the LDS current
+      // region even after rounding of o + dlt (a bound of exactly 1/2 could
+      // round to x1 = 3/2 and shift a quadratic stencil one node further)
+      small = small && dlt < R(0.49) && dlt > R(-0.49);
+      R x1 = o[d] + dlt;
+      if (x1 < R(-1) || x1 >= R(2)) {  // cannot happen below the Courant limit
+        raise_flag(flg, PIC_FLAG_OVERSPEED);
+        x1 = x1 < R(-1) ? R(-1) : R(1.5);
+      }
+      int s = x1 >= R(1) ? 1 : (x1 < R(0) ? -1 : 0);
+      R on = x1 - R(s);
+      if (on >= R(1)) {  // -tiny + 1 rounded up to 1
+        on = R(0);
+        s += 1;
+      }
+      sh[d] = s;
+      o1[d] = on;
+      int cn = c3[d] + s;
+      if (P.bc[d] == PIC_BC_PERIODIC) {
+        cn = wrap1(cn, P.n[d]);
+      } else if (cn < 0 || cn > P.n[d] - 2) {
+        absorbed = true;
+      }
+      c1[d] = cn;
+    }
+    const R vz = u[2] * ig;
+    if (fast && small) {
+      LdsCurrent<DIMS, ORDER, R> sink{
+          s_j, ((l[2] - G::j_lo_z) * G::jx + (l[1] - G::j_lo)) * G::jx + (l[0] - G::j_lo), s_j};
+      deposit<DIMS, ORDER, R>(sink, P.jfac, o, sh, o1, q, vz);
+    } else {
+      GlobalCurrent<R> sink{F.J, c3[0], c3[1], c3[2], P.n[0], P.n[1], P.n[2],
+                            open0, open1, open2, DIMS, 0, 0, 0};
+      deposit<DIMS, ORDER, R>(sink, P.jfac, o, sh, o1, q, vz);
+    }
+    // store the new state
+#pragma unroll
+    for (int c = 0; c < 3; ++c) pa.u[c][p] = u[c];
+#pragma unroll
+    for (int d = 0; d < DIMS; ++d) pa.off[d][p] = o1[d];
+    pa.cell[p] = absorbed ? -1 : c1[0] + P.n[0] * (c1[1] + P.n[1] * c1[2]);
+    const unsigned long long nslow = __popcll(__ballot(!fast));
+    if (nslow && (threadIdx.x & 63) == __ffsll(__ballot(!fast)) - 1)
+      atomicAdd(&flg->slowpath, nslow);
+  }
+  __syncthreads();
+
+  // flush the LDS current tile (its halo overlaps the neighbouring tiles')
+  for (int idx = threadIdx.x; idx < 3 * G::j_vol; idx += G::NT) {
+    const R v = (R)s_j[idx];
+    if (v == R(0)) continue;
+    const int comp = idx / G::j_vol;
+    const int r = idx - comp * G::j_vol;
+    const int lx = r % G::jx, ly = (r / G::jx) % G::jx, lz = r / (G::jx * G::jx);
+    const int ix = axis_slot(ox + G::j_lo + lx, P.n[0], open0, comp == 0);
+    const int iy = axis_slot(oy + G::j_lo + ly, P.n[1], open1, comp == 1);
+    const int iz = DIMS == 3 ? axis_slot(oz + G::j_lo_z + lz, P.n[2], open2, comp == 2) : 0;
+    if (ix < 0 || iy < 0 || iz < 0) continue;
+    atomic_add(&F.J[comp][ix + P.n[0] * (iy + P.n[1] * iz)], v);
+  }
+}
+
+template <typename R>
+__global__ void k_fill3(R* a, R* b, R* c, long n, R v) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    a[i] = v;
+    b[i] = v;
+    c[i] = v;
+  }
+}
+
+template <int DIMS, int ORDER, typename R>
+static int launch_pd(const pic_ctx* ctx, const pic_particles* p, const pic_fields* f, void* ws,
+                     hipStream_t s) {
+  using G = Geo<DIMS, ORDER, R>;
+  KParams<R> P = make_params<R>(ctx);
+  WsLayout L = ws_layout(ctx, p->np);
+  char* w = (char*)ws;
+  DParts<R> pa;
+  pa.cell = p->cell;
+  for (int d = 0; d < 3; ++d) {
+    pa.off[d] = (R*)p->off[d];
+    pa.u[d] = (R*)p->u[d];
+  }
+  pa.q = (R*)p->q;
+  pa.id = p->id;
+  DFields<R> F;
+  for (int c = 0; c < 3; ++c) {
+    F.E[c] = (R*)f->E[c];
+    F.B[c] = (R*)f->B[c];
+    F.J[c] = (R*)f->J[c];
+  }
+  const long ncell = (long)P.n[0] * P.n[1] * P.n[2];
+  k_fill3<R><<<dim3((unsigned)((ncell + 255) / 256 < 4096 ? (ncell + 255) / 256 : 4096)), dim3(256), 0, s>>>(
+      F.J[0], F.J[1], F.J[2], ncell, R(0));
+  const int grid = 8 * P.per_xcd;
+  k_push_deposit<DIMS, ORDER, R><<<dim3(grid), dim3(G::NT), 0, s>>>(
+      P, pa, F, (const int*)(w + L.starts), (DevFlags*)(w + L.flags));
+  return (int)hipGetLastError();
+}
+
+int launch_push_deposit(const pic_ctx* ctx, const pic_particles* p, const pic_fields* f, void* ws,
+                        hipStream_t s) {
+  const int D = ctx->cfg.dims, O = ctx->cfg.order;
+  const bool dbl = ctx->cfg.real_bytes == 8;
+#define PIC_PD(DD, OO)                                                            \
+  if (D == DD && O == OO)                                                         \
+    return dbl ? launch_pd<DD, OO, double>(ctx, p, f, ws, s)                     \
+               : launch_pd<DD, OO, float>(ctx, p, f, ws, s);
+  PIC_PD(2, 1) PIC_PD(2, 2) PIC_PD(2, 3) PIC_PD(3, 1) PIC_PD(3, 2) PIC_PD(3, 3)
+#undef PIC_PD
+  return (int)hipErrorInvalidValue;
+}
+
+}  // namespace pic

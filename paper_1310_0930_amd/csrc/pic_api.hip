@@ -1,0 +1,327 @@
+// C ABI of libpic: argument validation, workspace layout and dispatch.
+// Validation happens on the host before any HIP call, so configuration
+// errors are reported the same way with or without a device.
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+
+#include "pic_internal.h"
+
+namespace pic {
+long mur_len(const pic_config& cf);
+long diag_len(const pic_config& cf);
+
+static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+WsLayout ws_layout(const pic_ctx* ctx, int64_t np) {
+  const size_t R = (size_t)ctx->cfg.real_bytes;
+  WsLayout L;
+  size_t off = 0;
+  L.flags = off;
+  off = align256(off + sizeof(DevFlags));
+  L.counts = off;
+  off = align256(off + sizeof(int) * ((size_t)ctx->ntiles + 2));
+  L.starts = off;
+  off = align256(off + sizeof(int) * ((size_t)ctx->ntiles + 2));
+  L.mur_len = (size_t)mur_len(ctx->cfg);
+  L.mur = off;
+  off = align256(off + R * L.mur_len);
+  L.diag_len = (size_t)diag_len(ctx->cfg);
+  L.diag = off;
+  off = align256(off + sizeof(double) * L.diag_len);
+  const size_t n = np > 0 ? (size_t)np : 0;
+  L.tmp_cell = off;
+  off = align256(off + sizeof(int) * n);
+  L.tmp_id = off;
+  off = align256(off + sizeof(int) * n);
+  L.tmp_real = off;
+  off = align256(off + R * 7 * n);
+  L.total = off;
+  return L;
+}
+
+template <typename R>
+KParams<R> make_params(const pic_ctx* ctx) {
+  const pic_config& c = ctx->cfg;
+  KParams<R> P;
+  P.dims = c.dims;
+  P.order = c.order;
+  for (int d = 0; d < 3; ++d) {
+    P.n[d] = d < c.dims ? c.n[d] : 1;
+    P.bc[d] = d < c.dims ? c.bc[d] : PIC_BC_PERIODIC;
+    P.tile[d] = ctx->tile[d];
+    P.ntile[d] = ctx->ntile[d];
+    P.dtdx[d] = (R)(d < c.dims ? c.dt / c.dx[d] : 0.0);
+    P.jfac[d] = (R)(d < c.dims ? -c.dx[d] / c.dt : 0.0);
+  }
+  P.ntiles = ctx->ntiles;
+  P.per_xcd = (ctx->ntiles + 7) / 8;
+  P.dn0.init((uint32_t)P.n[0]);
+  P.dn1.init((uint32_t)P.n[1]);
+  P.hqm = (R)(0.5 * c.q_over_m * c.dt);
+  P.dt = (R)c.dt;
+  P.q_const = (R)c.q_const;
+  return P;
+}
+template KParams<float> make_params<float>(const pic_ctx*);
+template KParams<double> make_params<double>(const pic_ctx*);
+
+// Compile-time tile shape and LDS need of the selected kernel.
+template <int DIMS, int ORDER, typename R>
+static void geo_of(int* T, int* A, size_t* lds) {
+  using G = Geo<DIMS, ORDER, R>;
+  T[0] = T[1] = G::T;
+  T[2] = G::TZ;
+  *A = G::A;
+  *lds = G::lds_bytes;
+}
+
+static int kernel_geometry(const pic_config* c, int* T, int* A, size_t* lds) {
+  const bool dbl = c->real_bytes == 8;
+#define PIC_GEO(DD, OO)                                                 \
+  if (c->dims == DD && c->order == OO) {                                \
+    if (dbl)                                                            \
+      geo_of<DD, OO, double>(T, A, lds);                                \
+    else                                                                \
+      geo_of<DD, OO, float>(T, A, lds);                                 \
+    return 0;                                                           \
+  }
+  PIC_GEO(2, 1) PIC_GEO(2, 2) PIC_GEO(2, 3) PIC_GEO(3, 1) PIC_GEO(3, 2) PIC_GEO(3, 3)
+#undef PIC_GEO
+  return -1;
+}
+
+}  // namespace pic
+
+using namespace pic;
+
+static bool finite_pos(double v) { return isfinite(v) && v > 0.0; }
+
+static int validate_config(const pic_config* c) {
+  if (!c) return PIC_EINVAL;
+  if (c->dims != 2 && c->dims != 3) return PIC_EINVAL;
+  if (c->order < 1 || c->order > 3) return PIC_EINVAL;
+  if (c->real_bytes != 4 && c->real_bytes != 8) return PIC_EINVAL;
+  if (c->sort_every < 1) return PIC_EINVAL;
+  if (!isfinite(c->q_over_m) || !isfinite(c->q_const)) return PIC_EINVAL;
+  double ncell = 1.0;
+  for (int d = 0; d < c->dims; ++d) {
+    if (c->bc[d] != PIC_BC_PERIODIC && c->bc[d] != PIC_BC_OPEN) return PIC_EINVAL;
+    if (c->n[d] < (c->bc[d] == PIC_BC_OPEN ? 4 : 2)) return PIC_EINVAL;
+    if (!finite_pos(c->dx[d])) return PIC_EINVAL;
+    ncell *= (double)c->n[d];
+  }
+  if (c->dims == 2 && c->n[2] != 1) return PIC_EINVAL;
+  if (ncell >= 2147483647.0) return PIC_EINVAL;
+  if (!finite_pos(c->dt)) return PIC_EINVAL;
+  double s = 0.0;
+  for (int d = 0; d < c->dims; ++d) s += 1.0 / (c->dx[d] * c->dx[d]);
+  if (c->dt > (1.0 + 1e-12) / sqrt(s)) return PIC_ECOURANT;
+  int T[3], A;
+  size_t lds;
+  if (kernel_geometry(c, T, &A, &lds) != 0) return PIC_EINVAL;
+  for (int d = 0; d < 3; ++d)
+    if (c->tile[d] != 0 && c->tile[d] != T[d]) return PIC_EINVAL;
+  if (c->drift >= 0 && c->drift != A) return PIC_EINVAL;
+  if (lds > 160 * 1024) return PIC_ELDS;
+  return PIC_OK;
+}
+
+extern "C" {
+
+int pic_create(const pic_config* cfg, pic_ctx** out) {
+  if (!out) return PIC_EINVAL;
+  *out = nullptr;
+  const int v = validate_config(cfg);
+  if (v != PIC_OK) return v;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return PIC_EHIP;
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return PIC_EHIP;
+  pic_ctx* ctx = new (std::nothrow) pic_ctx();
+  if (!ctx) return PIC_EHIP;
+  ctx->cfg = *cfg;
+  if (cfg->dims == 2) {
+    ctx->cfg.n[2] = 1;
+    ctx->cfg.dx[2] = 1.0;
+    ctx->cfg.bc[2] = PIC_BC_PERIODIC;
+  }
+  ctx->device = dev;
+  ctx->cu_count = cus;
+  int T[3], A;
+  size_t lds;
+  kernel_geometry(cfg, T, &A, &lds);
+  ctx->ntiles = 1;
+  for (int d = 0; d < 3; ++d) {
+    ctx->tile[d] = T[d];
+    const int n = d < cfg->dims ? cfg->n[d] : 1;
+    ctx->ntile[d] = (n + T[d] - 1) / T[d];
+    ctx->ntiles *= ctx->ntile[d];
+  }
+  ctx->cfg.tile[0] = T[0];
+  ctx->cfg.tile[1] = T[1];
+  ctx->cfg.tile[2] = T[2];
+  ctx->cfg.drift = A;
+  ctx->steps_done = 0;
+  ctx->sorted_cell = nullptr;
+  ctx->sorted_ws = nullptr;
+  ctx->sorted_np = -1;
+  *out = ctx;
+  return PIC_OK;
+}
+
+int pic_destroy(pic_ctx* ctx) {
+  delete ctx;
+  return PIC_OK;
+}
+
+int pic_workspace_bytes(const pic_ctx* ctx, int64_t np, size_t* bytes) {
+  if (!ctx || !bytes || np < 0 || np >= 2147483647LL) return PIC_EINVAL;
+  *bytes = ws_layout(ctx, np).total;
+  return PIC_OK;
+}
+
+static int check_particles(const pic_ctx* ctx, const pic_particles* p) {
+  if (!p || p->np < 0 || p->np >= 2147483647LL) return PIC_EINVAL;
+  if (p->np == 0) return PIC_OK;
+  if (!p->cell) return PIC_EINVAL;
+  for (int d = 0; d < ctx->cfg.dims; ++d)
+    if (!p->off[d]) return PIC_EINVAL;
+  for (int c = 0; c < 3; ++c)
+    if (!p->u[c]) return PIC_EINVAL;
+  return PIC_OK;
+}
+
+static int check_fields(const pic_fields* f, bool need_j) {
+  if (!f) return PIC_EINVAL;
+  for (int c = 0; c < 3; ++c) {
+    if (!f->E[c] || !f->B[c]) return PIC_EINVAL;
+    if (need_j && !f->J[c]) return PIC_EINVAL;
+  }
+  return PIC_OK;
+}
+
+static int hip_status(int err) { return err == 0 ? PIC_OK : PIC_EHIP; }
+
+static int ensure_device(const pic_ctx* ctx) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return PIC_EHIP;
+  if (dev != ctx->device && hipSetDevice(ctx->device) != hipSuccess) return PIC_EHIP;
+  return PIC_OK;
+}
+
+int pic_sort(pic_ctx* ctx, pic_particles* p, void* ws, void* stream) {
+  if (!ctx || !ws) return PIC_EINVAL;
+  int v = check_particles(ctx, p);
+  if (v) return v;
+  if ((v = ensure_device(ctx))) return v;
+  v = hip_status(launch_sort(ctx, p, ws, (hipStream_t)stream));
+  if (v == PIC_OK) {
+    ctx->sorted_cell = p->cell;
+    ctx->sorted_ws = ws;
+    ctx->sorted_np = p->np;
+  }
+  return v;
+}
+
+int pic_push_deposit(pic_ctx* ctx, pic_particles* p, const pic_fields* f, void* ws, void* stream) {
+  if (!ctx || !ws) return PIC_EINVAL;
+  int v = check_particles(ctx, p);
+  if (v) return v;
+  if ((v = check_fields(f, true))) return v;
+  if (ctx->sorted_cell != p->cell || ctx->sorted_ws != ws || ctx->sorted_np != p->np)
+    return PIC_ESTATE;
+  if ((v = ensure_device(ctx))) return v;
+  return hip_status(launch_push_deposit(ctx, p, f, ws, (hipStream_t)stream));
+}
+
+int pic_field_advance(pic_ctx* ctx, pic_fields* f, void* ws, void* stream) {
+  if (!ctx || !ws) return PIC_EINVAL;
+  int v = check_fields(f, true);
+  if (v) return v;
+  if ((v = ensure_device(ctx))) return v;
+  return hip_status(launch_field_advance(ctx, f, ws, (hipStream_t)stream));
+}
+
+int pic_step(pic_ctx* ctx, pic_particles* p, pic_fields* f, int32_t nsteps, void* ws, void* stream) {
+  if (!ctx || !ws || nsteps < 0) return PIC_EINVAL;
+  int v = check_particles(ctx, p);
+  if (v) return v;
+  if ((v = check_fields(f, true))) return v;
+  for (int32_t s = 0; s < nsteps; ++s) {
+    const bool sorted = ctx->sorted_cell == p->cell && ctx->sorted_ws == ws && ctx->sorted_np == p->np;
+    if (!sorted || ctx->steps_done % ctx->cfg.sort_every == 0) {
+      if ((v = pic_sort(ctx, p, ws, stream))) return v;
+    }
+    if ((v = pic_push_deposit(ctx, p, f, ws, stream))) return v;
+    if ((v = pic_field_advance(ctx, f, ws, stream))) return v;
+    ctx->steps_done += 1;
+  }
+  return PIC_OK;
+}
+
+int pic_deposit_rho(pic_ctx* ctx, const pic_particles* p, double* rho, void* ws, void* stream) {
+  if (!ctx || !rho) return PIC_EINVAL;
+  int v = check_particles(ctx, p);
+  if (v) return v;
+  if ((v = ensure_device(ctx))) return v;
+  return hip_status(launch_deposit_rho(ctx, p, rho, ws, (hipStream_t)stream));
+}
+
+int pic_diagnostics(pic_ctx* ctx, const pic_particles* p, const pic_fields* f,
+                    const double* rho_prev, const double* gauss_ref, double* rho_out,
+                    double* gauss_out, pic_diag* out, void* ws, void* stream) {
+  if (!ctx || !ws || !rho_out || !out) return PIC_EINVAL;
+  int v = check_particles(ctx, p);
+  if (v) return v;
+  if ((v = check_fields(f, true))) return v;
+  if ((v = ensure_device(ctx))) return v;
+  memset(out, 0, sizeof(*out));
+  v = hip_status(launch_diagnostics(ctx, p, f, rho_prev, gauss_ref, rho_out, gauss_out, out, ws,
+                                    (hipStream_t)stream));
+  if (v) return v;
+  uint32_t flags = 0;
+  int64_t slow = 0;
+  v = pic_read_flags(ctx, ws, 0, &flags, &slow, stream);
+  out->flags = flags;
+  out->n_slowpath = slow;
+  return v == PIC_EDEVICE ? PIC_OK : v;
+}
+
+int pic_read_flags(pic_ctx* ctx, void* ws, int clear, uint32_t* flags, int64_t* n_slowpath,
+                   void* stream) {
+  if (!ctx || !ws) return PIC_EINVAL;
+  int v = ensure_device(ctx);
+  if (v) return v;
+  DevFlags h;
+  hipStream_t s = (hipStream_t)stream;
+  if (hipMemcpyAsync(&h, ws, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess) return PIC_EHIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return PIC_EHIP;
+  if (clear) {
+    DevFlags z;
+    memset(&z, 0, sizeof(z));
+    if (hipMemcpyAsync(ws, &z, sizeof(z), hipMemcpyHostToDevice, s) != hipSuccess) return PIC_EHIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return PIC_EHIP;
+  }
+  if (flags) *flags = h.flags;
+  if (n_slowpath) *n_slowpath = (int64_t)h.slowpath;
+  return h.flags ? PIC_EDEVICE : PIC_OK;
+}
+
+const char* pic_strerror(int status) {
+  switch (status) {
+    case PIC_OK: return "ok";
+    case PIC_EINVAL: return "invalid argument";
+    case PIC_ECOURANT: return "time step above the Courant limit";
+    case PIC_EHIP: return "HIP runtime error";
+    case PIC_ESTATE: return "call order violated (sort the particles first)";
+    case PIC_EDEVICE: return "device flags raised";
+    case PIC_ELDS: return "tile geometry exceeds the LDS of a compute unit";
+    default: return "unknown status";
+  }
+}
+
+}  // extern "C"

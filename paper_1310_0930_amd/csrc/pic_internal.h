@@ -1,0 +1,169 @@
+// Internal declarations of libpic (not part of the C ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/pic.h"
+
+namespace pic {
+
+// ------------------------------------------------------------------ geometry
+// Node offsets, relative to a particle's cell, that the order-n stencils can
+// touch.  Gather: union over the six Yee components of the nodes of the
+// (order+1)^D stencil at the component's own position.  Deposit: union over
+// the virtual segments of a path that moves at most half a cell per axis
+// (larger moves take the global-memory path).
+template <int ORDER>
+struct Reach {
+  static constexpr int g_lo = ORDER == 3 ? -2 : -1;
+  static constexpr int g_hi = ORDER == 1 ? 1 : 2;
+  static constexpr int d_lo = ORDER == 3 ? -2 : -1;
+  static constexpr int d_hi = ORDER == 3 ? 3 : 2;
+};
+
+// Tile shape (cells per axis) and drift allowance A: one workgroup owns the
+// particles binned to a tile at the last sort; those whose cell is still
+// within A cells of the tile run entirely out of LDS.  The LDS regions cover
+// the tile, A cells on each side and the stencil reach.  Sizes are
+// compile-time so that every stencil offset is an immediate of the LDS
+// instruction.
+template <int DIMS, int ORDER, typename R>
+struct Geo {
+  static constexpr bool big = (sizeof(R) == 8 && ORDER == 3);
+  static constexpr int T = DIMS == 3 ? 8 : 16;
+  static constexpr int TZ = DIMS == 3 ? T : 1;
+  static constexpr int A = DIMS == 3 ? (big ? 0 : 1) : 2;
+  static constexpr int AZ = DIMS == 3 ? A : 0;
+  using Rc = Reach<ORDER>;
+  // E/B region
+  static constexpr int ex = T + 2 * A + Rc::g_hi - Rc::g_lo;
+  static constexpr int ez = DIMS == 3 ? ex : 1;
+  static constexpr int e_lo = -A + Rc::g_lo;  // region origin relative to the tile origin
+  static constexpr int e_lo_z = DIMS == 3 ? e_lo : 0;
+  static constexpr int e_vol = ex * ex * ez;
+  // J region
+  static constexpr int jx = T + 2 * A + Rc::d_hi - Rc::d_lo;
+  static constexpr int jz = DIMS == 3 ? jx : 1;
+  static constexpr int j_lo = -A + Rc::d_lo;
+  static constexpr int j_lo_z = DIMS == 3 ? j_lo : 0;
+  static constexpr int j_vol = jx * jx * jz;
+  // E/B staged in the working precision; the current tile accumulates in
+  // double for both forms (gfx950 issues LDS double atomic adds ~17x faster
+  // than single-precision ones, and the in-tile sum gains precision)
+  static constexpr size_t lds_bytes = sizeof(R) * 6 * (size_t)e_vol + sizeof(double) * 3 * (size_t)j_vol;
+  // threads per workgroup: 8 wavefronts per CU in either case (two
+  // workgroups when their LDS fits twice in 160 KB), which leaves each lane
+  // up to 256 VGPRs for the unrolled gather and deposit
+  static constexpr int NT = DIMS == 2 ? 256 : (lds_bytes <= 80 * 1024 ? 256 : 512);
+};
+
+// Unsigned division by a runtime divisor through a precomputed multiplier
+// (round-up method of Granlund and Montgomery, "Division by invariant
+// integers using multiplication", 1994): q = (mulhi(m, a) + a) >> l, exact
+// for every 32-bit a.
+struct FastDiv {
+  uint32_t d, m, l;
+  __host__ void init(uint32_t div) {
+    d = div;
+    l = 0;
+    while ((1ull << l) < div) ++l;
+    m = (uint32_t)((((1ull << l) - div) << 32) / div + 1);
+  }
+  __device__ __forceinline__ uint32_t div(uint32_t a) const {
+    uint64_t t = (uint64_t)__umulhi(m, a) + a;
+    return (uint32_t)(t >> l);
+  }
+};
+
+// ------------------------------------------------------------------ params
+template <typename R>
+struct KParams {
+  int dims, order;
+  int n[3];
+  int bc[3];       // PIC_BC_*
+  int tile[3];     // cells per tile
+  int ntile[3];    // tiles per axis
+  int ntiles;      // product of ntile
+  int per_xcd;     // tiles per XCD slice (XCD-aware block remap)
+  FastDiv dn0, dn1;  // division by n0 and n1 (cell index decomposition)
+  R hqm;           // (q/m) dt / 2
+  R dtdx[3];       // dt / dx_d
+  R jfac[3];       // -dx_d / dt
+  R dt;
+  R q_const;
+};
+
+// Device-side particle and field pointers.
+template <typename R>
+struct DParts {
+  int32_t* cell;
+  R* off[3];
+  R* u[3];
+  R* q;  // may be null
+  int32_t* id;  // may be null
+};
+
+template <typename R>
+struct DFields {
+  R* E[3];
+  R* B[3];
+  R* J[3];
+};
+
+// Sticky flags and counters at the head of the workspace.
+struct DevFlags {
+  unsigned int flags;
+  unsigned int pad;
+  unsigned long long slowpath;
+  unsigned long long pad2[6];
+};
+
+// ------------------------------------------------------------------ workspace
+struct WsLayout {
+  size_t flags;      // DevFlags
+  size_t counts;     // int32[ntiles + 2]   per-tile counts / cursors
+  size_t starts;     // int32[ntiles + 2]   bin starts (ntiles + 1 used, last = dead bin end)
+  size_t tmp_cell;   // int32[np]
+  size_t tmp_real;   // R[np * 7]  off[3], u[3], q
+  size_t tmp_id;     // int32[np]
+  size_t mur;        // R[mur_len]  saved E planes next to open faces
+  size_t diag;       // double[diag_len]  reduction partials
+  size_t total;
+  size_t mur_len;
+  size_t diag_len;
+};
+
+}  // namespace pic
+
+struct pic_ctx {
+  pic_config cfg;
+  int device;
+  int ntile[3];
+  int ntiles;
+  int tile[3];
+  int64_t steps_done;      // steps taken through pic_step (drives sort_every)
+  // sorted-state tracking: pic_push_deposit needs bins that match the arrays
+  const void* sorted_cell;
+  const void* sorted_ws;
+  int64_t sorted_np;
+  int64_t sorted_cap;
+  int cu_count;
+};
+
+namespace pic {
+WsLayout ws_layout(const pic_ctx* ctx, int64_t np);
+
+// launchers (return hipError_t as int)
+int launch_sort(const pic_ctx* ctx, const pic_particles* p, void* ws, hipStream_t s);
+int launch_push_deposit(const pic_ctx* ctx, const pic_particles* p, const pic_fields* f,
+                        void* ws, hipStream_t s);
+int launch_field_advance(const pic_ctx* ctx, const pic_fields* f, void* ws, hipStream_t s);
+int launch_deposit_rho(const pic_ctx* ctx, const pic_particles* p, double* rho, void* ws,
+                       hipStream_t s);
+int launch_diagnostics(const pic_ctx* ctx, const pic_particles* p, const pic_fields* f,
+                       const double* rho_prev, const double* gauss_ref, double* rho_out,
+                       double* gauss_out, pic_diag* out, void* ws, hipStream_t s);
+
+template <typename R>
+KParams<R> make_params(const pic_ctx* ctx);
+}  // namespace pic

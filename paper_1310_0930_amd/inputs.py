@@ -95,6 +95,11 @@ class Workload:
         a, b, c = self.particle_cells()
         return a * b * c * self.ppc
 
+    @property
+    def q_const(self) -> float:
+        """Charge of one macro-electron at density n0 = 1, rounded to FP32."""
+        return float(np.float32(-1.0 / self.ppc))
+
     def with_(self, **kw) -> "Workload":
         return replace(self, **kw)
 
@@ -214,12 +219,11 @@ def make_plasma(w: Workload, slabs: range | None = None, quiet: bool = False) ->
         if w.u_th > 0.0:
             u[:, lo:hi] = _round32(rng.normal(0.0, w.u_th, size=(3, per_slab)))
     q = None
-    q_const = -1.0 / w.ppc
     if w.ramp_cells > 0.0:
-        X = Plasma(cell, off, u, None, q_const).global_positions(w)[:, 0]
+        X = Plasma(cell, off, u, None, w.q_const).global_positions(w)[:, 0]
         dens = np.clip(X / w.ramp_cells, 0.0, 1.0)
         q = _round32(-dens / w.ppc)
-    return Plasma(cell, off, u, q, float(np.float32(q_const)))
+    return Plasma(cell, off, u, q, w.q_const)
 
 
 def laser_fields(w: Workload, a0: float | None = None) -> tuple[np.ndarray, np.ndarray]:
