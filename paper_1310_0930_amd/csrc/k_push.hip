@@ -281,157 +281,347 @@ __device__ __forceinline__ void boris(R hqm, R* u, const R* E, const R* B) {
 // shape differences along c and A_c the time-averaged transverse weight.
 // Every segment end is expressed in the piece frame of its stencil: crossing
 // points exactly on their plane, other coordinates once per point.
-template <int DIMS, int ORDER, typename R, class Sink>
-__device__ __forceinline__ void deposit(Sink sink, const R* jfac, const R* o0,
-                                        const int* sh, const R* o1, R q, R vz) {
-  constexpr int M = ORDER + 1;
-  constexpr bool odd = ORDER & 1;
+template <int DIMS, typename R>
+struct Split {
   int k0[3], k1[3];
-  R xi0[3], xi1[3], dl[3], pk0[3], pk1[3], fr[3];
+  R xi0[3], xi1[3], dl[3], pk0[3], pk1[3];
   bool cr[3];
+  int jd[3];
+  R tb[DIMS + 2];
+  int m;  // crossings: the path has m + 1 segments
+};
+
+template <int DIMS, int ORDER, typename R>
+__device__ __forceinline__ void split_path(Split<DIMS, R>& S, const R* o0, const int* sh,
+                                           const R* o1) {
+  constexpr bool odd = ORDER & 1;
+  R fr[3];
 #pragma unroll
   for (int d = 0; d < DIMS; ++d) {
-    k0[d] = piece_node<ORDER>(o0[d], xi0[d]);
-    k1[d] = sh[d] + piece_node<ORDER>(o1[d], xi1[d]);
-    dl[d] = R(k1[d] - k0[d]) + (xi1[d] - xi0[d]);
-    cr[d] = false;
+    S.k0[d] = piece_node<ORDER>(o0[d], S.xi0[d]);
+    S.k1[d] = sh[d] + piece_node<ORDER>(o1[d], S.xi1[d]);
+    S.dl[d] = R(S.k1[d] - S.k0[d]) + (S.xi1[d] - S.xi0[d]);
+    S.cr[d] = false;
     fr[d] = R(2);
-    pk0[d] = pk1[d] = R(0);
-    if (k1[d] != k0[d]) {
-      const bool up = k1[d] > k0[d];
-      pk0[d] = odd ? (up ? R(1) : R(0)) : (up ? R(0.5) : R(-0.5));
-      pk1[d] = odd ? (up ? R(0) : R(1)) : (up ? R(-0.5) : R(0.5));
-      const R f = (pk0[d] - xi0[d]) / dl[d];
+    S.pk0[d] = S.pk1[d] = R(0);
+    if (S.k1[d] != S.k0[d]) {
+      const bool up = S.k1[d] > S.k0[d];
+      S.pk0[d] = odd ? (up ? R(1) : R(0)) : (up ? R(0.5) : R(-0.5));
+      S.pk1[d] = odd ? (up ? R(0) : R(1)) : (up ? R(-0.5) : R(0.5));
+      const R f = (S.pk0[d] - S.xi0[d]) / S.dl[d];
       if (f > R(0) && f < R(1)) {
-        cr[d] = true;
+        S.cr[d] = true;
         fr[d] = f;
       } else if (!(f > R(0))) {  // starts on the plane: the path is in piece k1
-        k0[d] = k1[d];
-        xi0[d] = pk1[d];
+        S.k0[d] = S.k1[d];
+        S.xi0[d] = S.pk1[d];
       } else {  // ends on the plane: the path is in piece k0
-        k1[d] = k0[d];
-        xi1[d] = pk0[d];
+        S.k1[d] = S.k0[d];
+        S.xi1[d] = S.pk0[d];
       }
     }
   }
   // ascending crossing fractions; jd[d] = index of axis d's crossing point
-  R tb[DIMS + 2];
-  int jd[3] = {DIMS + 2, DIMS + 2, DIMS + 2};
-  int m = 0;
-  tb[0] = R(0);
+  S.jd[0] = S.jd[1] = S.jd[2] = DIMS + 2;
+  S.m = 0;
+  S.tb[0] = R(0);
 #pragma unroll
   for (int d = 0; d < DIMS; ++d) {
-    if (!cr[d]) continue;
+    if (!S.cr[d]) continue;
     int rank = 1;
 #pragma unroll
     for (int e = 0; e < DIMS; ++e)
-      if (e != d && cr[e] && (fr[e] < fr[d] || (fr[e] == fr[d] && e < d))) ++rank;
-    jd[d] = rank;
-    ++m;
+      if (e != d && S.cr[e] && (fr[e] < fr[d] || (fr[e] == fr[d] && e < d))) ++rank;
+    S.jd[d] = rank;
+    ++S.m;
   }
+  // tb[j] = the j-th crossing fraction, 1 from tb[m+1] on (selects, so that
+  // the struct stays in registers)
 #pragma unroll
-  for (int d = 0; d < DIMS; ++d)
-    if (cr[d]) tb[jd[d]] = fr[d];
-  tb[m + 1] = R(1);
-
-  for (int s = 0; s <= m; ++s) {
-    // mean weight Sm = S0 + dS/2 and dS/12: the Esirkepov transverse factor
-    // S0a S0b + (dSa S0b + S0a dSb)/2 + dSa dSb/3 equals Sma Smb + dSa dSb/12
-    R Sm[3][M], dS[3][M], d12[3][M];
-    int base[3] = {0, 0, 0};
+  for (int j = 1; j < DIMS + 2; ++j) {
+    R v = R(1);
 #pragma unroll
-    for (int d = 0; d < DIMS; ++d) {
-      const bool f1 = cr[d] && s >= jd[d];
-      R xa, xb;
-      if (s == 0)
-        xa = xi0[d];
-      else if (cr[d] && s == jd[d])
-        xa = pk1[d];
-      else
-        xa = f1 ? xi1[d] - (R(1) - tb[s]) * dl[d] : xi0[d] + tb[s] * dl[d];
-      if (s == m)
-        xb = xi1[d];
-      else if (cr[d] && s + 1 == jd[d])
-        xb = pk0[d];
-      else
-        xb = f1 ? xi1[d] - (R(1) - tb[s + 1]) * dl[d] : xi0[d] + tb[s + 1] * dl[d];
-      base[d] = (f1 ? k1[d] : k0[d]) - ORDER / 2;
-      R S0[M];
-      shape<ORDER>(xa, S0);
-      dshape<ORDER>(xa, xb, dS[d]);
-#pragma unroll
-      for (int i = 0; i < M; ++i) {
-        Sm[d][i] = S0[i] + R(0.5) * dS[d][i];
-        d12[d][i] = R(1.0 / 12.0) * dS[d][i];
-      }
-    }
-    Sink sk = sink;
-    sk.segment(base);
-    if (DIMS == 3) {
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const int a = (c + 1) % 3, b = (c + 2) % 3;
-        R P[ORDER];
-        R run = R(0);
-#pragma unroll
-        for (int i = 0; i < ORDER; ++i) {
-          run += dS[c][i];
-          P[i] = q * jfac[c] * run;
-        }
-#pragma unroll
-        for (int ib = 0; ib < M; ++ib)
-#pragma unroll
-          for (int ia = 0; ia < M; ++ia) {
-            const R A = Sm[a][ia] * Sm[b][ib] + d12[a][ia] * dS[b][ib];
-#pragma unroll
-            for (int ic = 0; ic < ORDER; ++ic) {
-              int L[3];
-              L[c] = ic;
-              L[a] = ia;
-              L[b] = ib;
-              sk.add(c, L[0], L[1], L[2], P[ic] * A);
-            }
-          }
-      }
-    } else {
-#pragma unroll
-      for (int c = 0; c < 2; ++c) {
-        const int a = 1 - c;
-        R P[ORDER];
-        R run = R(0);
-#pragma unroll
-        for (int i = 0; i < ORDER; ++i) {
-          run += dS[c][i];
-          P[i] = q * jfac[c] * run;
-        }
-#pragma unroll
-        for (int ia = 0; ia < M; ++ia) {
-#pragma unroll
-          for (int ic = 0; ic < ORDER; ++ic) {
-            int L[2];
-            L[c] = ic;
-            L[a] = ia;
-            sk.add(c, L[0], L[1], 0, P[ic] * Sm[a][ia]);
-          }
-        }
-      }
-      const R fz = q * vz * (tb[s + 1] - tb[s]);
-#pragma unroll
-      for (int j = 0; j < M; ++j)
-#pragma unroll
-        for (int i = 0; i < M; ++i)
-          sk.add(2, i, j, 0, fz * (Sm[0][i] * Sm[1][j] + d12[0][i] * dS[1][j]));
-    }
+    for (int d = 0; d < DIMS; ++d)
+      if (S.cr[d] && S.jd[d] == j) v = fr[d];
+    S.tb[j] = v;
   }
 }
 
-// ------------------------------------------------------------------ kernel
+// End points of segment s in its piece frame, its first stencil node and
+// its fraction of the time step.
 template <int DIMS, int ORDER, typename R>
-__global__ void __launch_bounds__((Geo<DIMS, ORDER, R>::NT)) k_push_deposit(
-    KParams<R> P, DParts<R> pa, DFields<R> F, const int* __restrict__ starts, DevFlags* flg) {
+__device__ __forceinline__ void segment_ends(const Split<DIMS, R>& S, int s, R* xa, R* xb,
+                                             int* base, R& ft) {
+  R ta = R(0), tbb = R(1);
+#pragma unroll
+  for (int j = 0; j < DIMS + 2; ++j) {
+    if (j == s) ta = S.tb[j];
+    if (j == s + 1) tbb = S.tb[j];
+  }
+  ft = tbb - ta;
+  base[0] = base[1] = base[2] = 0;
+  xa[2] = xb[2] = R(0);
+#pragma unroll
+  for (int d = 0; d < DIMS; ++d) {
+    const bool f1 = S.cr[d] && s >= S.jd[d];
+    R a, b;
+    if (s == 0)
+      a = S.xi0[d];
+    else if (S.cr[d] && s == S.jd[d])
+      a = S.pk1[d];
+    else
+      a = f1 ? S.xi1[d] - (R(1) - ta) * S.dl[d] : S.xi0[d] + ta * S.dl[d];
+    if (s == S.m)
+      b = S.xi1[d];
+    else if (S.cr[d] && s + 1 == S.jd[d])
+      b = S.pk0[d];
+    else
+      b = f1 ? S.xi1[d] - (R(1) - tbb) * S.dl[d] : S.xi0[d] + tbb * S.dl[d];
+    base[d] = (f1 ? S.k1[d] : S.k0[d]) - ORDER / 2;
+    xa[d] = a;
+    xb[d] = b;
+  }
+}
+
+// Esirkepov current of one segment whose first stencil node the sink holds.
+// fz (2D only) = q v_z times the segment's time fraction.
+template <int DIMS, int ORDER, typename R, class Sink>
+__device__ __forceinline__ void deposit_segment(const Sink& sk, const R* jfac, const R* xa,
+                                                const R* xb, R q, R fz) {
+  constexpr int M = ORDER + 1;
+  // mean weight Sm = S0 + dS/2 and dS/12: the Esirkepov transverse factor
+  // S0a S0b + (dSa S0b + S0a dSb)/2 + dSa dSb/3 equals Sma Smb + dSa dSb/12
+  R Sm[3][M], dS[3][M], d12[3][M];
+#pragma unroll
+  for (int d = 0; d < DIMS; ++d) {
+    R S0[M];
+    shape<ORDER>(xa[d], S0);
+    dshape<ORDER>(xa[d], xb[d], dS[d]);
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+      Sm[d][i] = S0[i] + R(0.5) * dS[d][i];
+      d12[d][i] = R(1.0 / 12.0) * dS[d][i];
+    }
+  }
+  if (DIMS == 3) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int a = (c + 1) % 3, b = (c + 2) % 3;
+      R P[ORDER];
+      R run = R(0);
+#pragma unroll
+      for (int i = 0; i < ORDER; ++i) {
+        run += dS[c][i];
+        P[i] = q * jfac[c] * run;
+      }
+#pragma unroll
+      for (int ib = 0; ib < M; ++ib)
+#pragma unroll
+        for (int ia = 0; ia < M; ++ia) {
+          const R A = Sm[a][ia] * Sm[b][ib] + d12[a][ia] * dS[b][ib];
+#pragma unroll
+          for (int ic = 0; ic < ORDER; ++ic) {
+            int L[3];
+            L[c] = ic;
+            L[a] = ia;
+            L[b] = ib;
+            sk.add(c, L[0], L[1], L[2], P[ic] * A);
+          }
+        }
+    }
+  } else {
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const int a = 1 - c;
+      R P[ORDER];
+      R run = R(0);
+#pragma unroll
+      for (int i = 0; i < ORDER; ++i) {
+        run += dS[c][i];
+        P[i] = q * jfac[c] * run;
+      }
+#pragma unroll
+      for (int ia = 0; ia < M; ++ia) {
+#pragma unroll
+        for (int ic = 0; ic < ORDER; ++ic) {
+          int L[2];
+          L[c] = ic;
+          L[a] = ia;
+          sk.add(c, L[0], L[1], 0, P[ic] * Sm[a][ia]);
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < M; ++j)
+#pragma unroll
+      for (int i = 0; i < M; ++i)
+        sk.add(2, i, j, 0, fz * (Sm[0][i] * Sm[1][j] + d12[0][i] * dS[1][j]));
+  }
+}
+
+// The whole path, segment after segment (global-memory path).
+template <int DIMS, int ORDER, typename R, class Sink>
+__device__ __forceinline__ void deposit(Sink sink, const R* jfac, const R* o0,
+                                        const int* sh, const R* o1, R q, R vz) {
+  Split<DIMS, R> S;
+  split_path<DIMS, ORDER, R>(S, o0, sh, o1);
+  for (int s = 0; s <= S.m; ++s) {
+    R xa[3], xb[3], ft;
+    int base[3];
+    segment_ends<DIMS, ORDER, R>(S, s, xa, xb, base, ft);
+    sink.segment(base);
+    deposit_segment<DIMS, ORDER, R>(sink, jfac, xa, xb, q, q * vz * ft);
+  }
+}
+
+// ------------------------------------------------------------------ particle
+// Particle state in registers.
+template <typename R>
+struct PState {
+  int cl;
+  R o[3];
+  R u[3];
+  R q;
+};
+
+template <int DIMS, typename R>
+__device__ __forceinline__ PState<R> load_particle(const DParts<R>& pa, int p, R q_const) {
+  PState<R> s;
+  s.cl = pa.cell[p];
+  s.o[0] = s.o[1] = s.o[2] = R(0);
+#pragma unroll
+  for (int d = 0; d < DIMS; ++d) s.o[d] = pa.off[d][p];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) s.u[c] = pa.u[c][p];
+  s.q = pa.q ? pa.q[p] : q_const;
+  return s;
+}
+
+// Cell index -> (ix, iy, iz); false (and a raised flag) for a state the
+// kernels must not index with.
+template <int DIMS, typename R>
+__device__ __forceinline__ bool decode(const KParams<R>& P, const PState<R>& s, int* c3,
+                                       DevFlags* flg) {
+  const int ncell = P.n[0] * P.n[1] * P.n[2];
+  bool bad = s.cl >= ncell;
+#pragma unroll
+  for (int d = 0; d < DIMS; ++d) bad |= !(s.o[d] >= R(0) && s.o[d] < R(1));
+  if (bad) {
+    raise_flag(flg, s.cl >= ncell ? PIC_FLAG_CELL : PIC_FLAG_OFFSET);
+    return false;
+  }
+  const uint32_t rest = P.dn0.div((uint32_t)s.cl);
+  c3[0] = s.cl - (int)rest * P.n[0];
+  c3[1] = DIMS == 3 ? (int)(rest - P.dn1.div(rest) * P.n[1]) : (int)rest;
+  c3[2] = DIMS == 3 ? (int)P.dn1.div(rest) : 0;
+  return true;
+}
+
+// Boris push and move of one particle: u^{n-1/2} -> u^{n+1/2}, then the new
+// offsets o1 and cell shifts sh (the deposit uses exactly these stored
+// values).  Returns false for a non-finite momentum.
+template <int DIMS, typename R>
+__device__ __forceinline__ bool push_move(const KParams<R>& P, PState<R>& s, const R* Ep,
+                                          const R* Bp, int* sh, R* o1, R& vz, bool& small,
+                                          DevFlags* flg) {
+  boris<R>(P.hqm, s.u, Ep, Bp);
+  const R gam = sqrt(R(1) + s.u[0] * s.u[0] + s.u[1] * s.u[1] + s.u[2] * s.u[2]);
+  if (!isfinite(gam)) {
+    raise_flag(flg, PIC_FLAG_NONFINITE);
+    return false;
+  }
+  const R ig = R(1) / gam;
+  small = true;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    sh[d] = 0;
+    o1[d] = R(0);
+  }
+#pragma unroll
+  for (int d = 0; d < DIMS; ++d) {
+    const R dlt = s.u[d] * ig * P.dtdx[d];
+    // |move| < 0.49 keeps every segment stencil inside the LDS current
+    // region even after rounding of o + dlt (a bound of exactly 1/2 could
+    // round to x1 = 3/2 and shift a quadratic stencil one node further)
+    small = small && dlt < R(0.49) && dlt > R(-0.49);
+    R x1 = s.o[d] + dlt;
+    if (x1 < R(-1) || x1 >= R(2)) {  // cannot happen below the Courant limit
+      raise_flag(flg, PIC_FLAG_OVERSPEED);
+      x1 = x1 < R(-1) ? R(-1) : R(1.5);
+    }
+    int k = x1 >= R(1) ? 1 : (x1 < R(0) ? -1 : 0);
+    R on = x1 - R(k);
+    if (on >= R(1)) {  // -tiny + 1 rounded up to 1
+      on = R(0);
+      k += 1;
+    }
+    sh[d] = k;
+    o1[d] = on;
+  }
+  vz = s.u[2] * ig;
+  return true;
+}
+
+// New cell after the shifts (periodic wrap; -1 when absorbed at an open face).
+template <int DIMS, typename R>
+__device__ __forceinline__ int new_cell(const KParams<R>& P, const int* c3, const int* sh) {
+  int c1[3] = {c3[0], c3[1], c3[2]};
+  bool absorbed = false;
+#pragma unroll
+  for (int d = 0; d < DIMS; ++d) {
+    int cn = c3[d] + sh[d];
+    if (P.bc[d] == PIC_BC_PERIODIC)
+      cn = wrap1(cn, P.n[d]);
+    else if (cn < 0 || cn > P.n[d] - 2)
+      absorbed = true;
+    c1[d] = cn;
+  }
+  return absorbed ? -1 : c1[0] + P.n[0] * (c1[1] + P.n[1] * c1[2]);
+}
+
+template <int DIMS, typename R>
+__device__ __forceinline__ void store_particle(const DParts<R>& pa, int p, const PState<R>& s,
+                                               const R* o1, int cell) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) pa.u[c][p] = s.u[c];
+#pragma unroll
+  for (int d = 0; d < DIMS; ++d) pa.off[d][p] = o1[d];
+  pa.cell[p] = cell;
+}
+
+// ------------------------------------------------------------------ kernels
+// Per-wavefront queue of virtual segments beyond a particle's first.  About
+// one particle in thirty crosses a stencil-switch plane in a thermal plasma,
+// but that puts a crossing in almost every 64-lane wavefront: depositing the
+// extra segments in place would run the deposit twice per wavefront.
+// Instead every lane deposits its first segment, extra segments are queued
+// (structure of arrays in LDS) and deposited 64 at a time.  Used where the
+// queue still fits next to the tile's field and current regions.
+template <int DIMS, int ORDER, typename R>
+struct SegQueue {
   using G = Geo<DIMS, ORDER, R>;
+  static constexpr int CAP = 80;  // records per wavefront
+  static constexpr int NW = G::NT / 64;
+  static constexpr int NV = 8;  // q, fz, xa[3], xb[3]
+  static constexpr size_t bytes = (size_t)NW * CAP * (sizeof(int) + NV * sizeof(R));
+  static constexpr bool on = G::lds_bytes + bytes <= 160 * 1024;
+  static constexpr int LEN = on ? NW * CAP : 1;
+};
+
+// Tile kernel: one workgroup per tile; particles within the drift allowance
+// of the tile run out of LDS.  Any other particle (drifted further, or moving
+// half a cell or more in one step) is left untouched and appended to the
+// deferred list for k_push_deferred.
+template <int DIMS, int ORDER, typename R>
+__global__ void __launch_bounds__((Geo<DIMS, ORDER, R>::NT)) k_push_tile(
+    KParams<R> P, DParts<R> pa, DFields<R> F, const int* __restrict__ starts,
+    int* __restrict__ deferred, DevFlags* flg) {
+  using G = Geo<DIMS, ORDER, R>;
+  using Q = SegQueue<DIMS, ORDER, R>;
   __shared__ R s_eb[6 * G::e_vol];
   __shared__ double s_j[3 * G::j_vol];
+  __shared__ int q_idx[Q::LEN];
+  __shared__ R q_val[Q::NV][Q::LEN];
 
   // XCD-aware remap: consecutive block ids go round-robin over the 8 XCDs,
   // so give each XCD a contiguous range of tiles (neighbouring tiles share
@@ -443,57 +633,64 @@ __global__ void __launch_bounds__((Geo<DIMS, ORDER, R>::NT)) k_push_deposit(
   const int tx = tile % P.ntile[0];
   const int ty = (tile / P.ntile[0]) % P.ntile[1];
   const int tz = tile / (P.ntile[0] * P.ntile[1]);
-  const int ox = tx * G::T, oy = ty * G::T, oz = tz * G::TZ;
+  const int org[3] = {tx * G::T, ty * G::T, tz * G::TZ};
   const int open0 = P.bc[0] == PIC_BC_OPEN, open1 = P.bc[1] == PIC_BC_OPEN;
   const int open2 = DIMS == 3 && P.bc[2] == PIC_BC_OPEN;
 
-  // stage E and B of tile + halo (zero outside open faces)
-  for (int idx = threadIdx.x; idx < 6 * G::e_vol; idx += G::NT) {
-    const int comp = idx / G::e_vol;
-    const int r = idx - comp * G::e_vol;
-    const int lx = r % G::ex, ly = (r / G::ex) % G::ex, lz = r / (G::ex * G::ex);
-    const int c = comp < 3 ? comp : comp - 3;
-    const bool isb = comp >= 3;
-    const int ix = axis_slot(ox + G::e_lo + lx, P.n[0], open0, isb ? (c != 0) : (c == 0));
-    const int iy = axis_slot(oy + G::e_lo + ly, P.n[1], open1, isb ? (c != 1) : (c == 1));
-    const int iz = DIMS == 3 ? axis_slot(oz + G::e_lo_z + lz, P.n[2], open2, isb ? (c != 2) : (c == 2))
-                             : 0;
-    R v = R(0);
-    if (ix >= 0 && iy >= 0 && iz >= 0) {
-      const R* f = isb ? F.B[c] : F.E[c];
-      v = f[ix + P.n[0] * (iy + P.n[1] * iz)];
+  // stage E and B of tile + halo (zero outside open faces); every load of a
+  // thread is issued before the first LDS store so that their latencies
+  // overlap
+  constexpr int NSTAGE = (6 * G::e_vol + G::NT - 1) / G::NT;
+  R stage[NSTAGE];
+#pragma unroll
+  for (int k = 0; k < NSTAGE; ++k) {
+    const int idx = threadIdx.x + k * G::NT;
+    stage[k] = R(0);
+    if (idx < 6 * G::e_vol) {
+      const int comp = idx / G::e_vol;
+      const int r = idx - comp * G::e_vol;
+      const int lx = r % G::ex, ly = (r / G::ex) % G::ex, lz = r / (G::ex * G::ex);
+      const int c = comp < 3 ? comp : comp - 3;
+      const bool isb = comp >= 3;
+      const int ix = axis_slot(org[0] + G::e_lo + lx, P.n[0], open0, isb ? (c != 0) : (c == 0));
+      const int iy = axis_slot(org[1] + G::e_lo + ly, P.n[1], open1, isb ? (c != 1) : (c == 1));
+      const int iz = DIMS == 3 ? axis_slot(org[2] + G::e_lo_z + lz, P.n[2], open2,
+                                           isb ? (c != 2) : (c == 2))
+                               : 0;
+      if (ix >= 0 && iy >= 0 && iz >= 0) {
+        const R* f = isb ? F.B[c] : F.E[c];
+        stage[k] = f[ix + P.n[0] * (iy + P.n[1] * iz)];
+      }
     }
-    s_eb[idx] = v;
+  }
+#pragma unroll
+  for (int k = 0; k < NSTAGE; ++k) {
+    const int idx = threadIdx.x + k * G::NT;
+    if (idx < 6 * G::e_vol) s_eb[idx] = stage[k];
   }
   for (int idx = threadIdx.x; idx < 3 * G::j_vol; idx += G::NT) s_j[idx] = 0.0;
   __syncthreads();
 
-  const int ncell = P.n[0] * P.n[1] * P.n[2];
-  for (int p = pbeg + threadIdx.x; p < pend; p += G::NT) {
-    const int cl = pa.cell[p];
-    if (cl < 0) continue;  // absorbed
-    R o[3] = {R(0), R(0), R(0)}, u[3];
-#pragma unroll
-    for (int d = 0; d < DIMS; ++d) o[d] = pa.off[d][p];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) u[c] = pa.u[c][p];
-    const R q = pa.q ? pa.q[p] : P.q_const;
-    bool bad = cl >= ncell;
-#pragma unroll
-    for (int d = 0; d < DIMS; ++d) bad |= !(o[d] >= R(0) && o[d] < R(1));
-    if (bad) {  // keeps every index below in bounds
-      raise_flag(flg, cl >= ncell ? PIC_FLAG_CELL : PIC_FLAG_OFFSET);
-      continue;
-    }
-    const uint32_t rest = P.dn0.div((uint32_t)cl);
-    int c3[3];
-    c3[0] = cl - (int)rest * P.n[0];
-    c3[1] = DIMS == 3 ? (int)(rest - P.dn1.div(rest) * P.n[1]) : (int)rest;
-    c3[2] = DIMS == 3 ? (int)P.dn1.div(rest) : 0;
+  const int lane = threadIdx.x & 63;
+  const int qb = (threadIdx.x >> 6) * Q::CAP;  // this wavefront's queue
+  int qn = 0;                                  // queued records (wavefront-uniform)
+  LdsCurrent<DIMS, ORDER, R> qsink{s_j, 0, s_j};
+
+  // The loop is uniform per wavefront (lanes past the end are idle) so that
+  // whole-wavefront queue rounds see every lane.  The next particle's state
+  // is loaded one iteration ahead.
+  int p = pbeg + threadIdx.x;
+  PState<R> nxt;
+  if (p < pend) nxt = load_particle<DIMS, R>(pa, p, P.q_const);
+  for (; p - lane < pend; p += G::NT) {
+    PState<R> s = nxt;
+    if (p + G::NT < pend) nxt = load_particle<DIMS, R>(pa, p + G::NT, P.q_const);
+    bool valid = p < pend && s.cl >= 0;
+    int c3[3] = {0, 0, 0};
+    if (valid) valid = decode<DIMS, R>(P, s, c3, flg);
     // position relative to the tile origin (periodic image inside the window)
-    int l[3];
+    int l[3] = {0, 0, 0};
     bool fast = true;
-    const int org[3] = {ox, oy, oz};
 #pragma unroll
     for (int d = 0; d < DIMS; ++d) {
       const int Td = d == 2 ? G::TZ : G::T;
@@ -506,79 +703,91 @@ __global__ void __launch_bounds__((Geo<DIMS, ORDER, R>::NT)) k_push_deposit(
       l[d] = v;
       fast = fast && v >= -Ad && v < Td + Ad;
     }
-    if (DIMS == 2) l[2] = 0;
-
-    R Ep[3], Bp[3];
-    if (fast) {
+    R o1[3] = {R(0), R(0), R(0)}, vz = R(0);
+    int sh[3] = {0, 0, 0};
+    if (valid && !fast) {  // leave the state as it was; the global-memory kernel redoes it
+      deferred[atomicAdd(&flg->ndefer, 1u)] = p;
+      valid = false;
+    }
+    if (valid) {
       LdsFields<DIMS, ORDER, R> acc{
           s_eb, ((l[2] - G::e_lo_z) * G::ex + (l[1] - G::e_lo)) * G::ex + (l[0] - G::e_lo)};
-      gather<DIMS, ORDER, R>(acc, o, Ep, Bp);
-    } else {
-      GlobalFields<R> acc{F.E, F.B, c3[0], c3[1], c3[2], P.n[0], P.n[1], P.n[2],
-                          open0, open1, open2, DIMS};
-      gather<DIMS, ORDER, R>(acc, o, Ep, Bp);
-    }
-    boris<R>(P.hqm, u, Ep, Bp);
-    const R gam = sqrt(R(1) + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-    if (!isfinite(gam)) {
-      raise_flag(flg, PIC_FLAG_NONFINITE);
-      pa.cell[p] = -1;
-      continue;
-    }
-    const R ig = R(1) / gam;
-    // move in cell units; the new offset and cell shift are exact functions
-    // of the rounded sum, and the deposit uses exactly the stored result
-    int sh[3] = {0, 0, 0};
-    R o1[3] = {R(0), R(0), R(0)};
-    bool small = true, absorbed = false;
-    int c1[3] = {c3[0], c3[1], c3[2]};
-#pragma unroll
-    for (int d = 0; d < DIMS; ++d) {
-      const R dlt = u[d] * ig * P.dtdx[d];
-      // |move| < 0.49 keeps every segment stencil inside the LDS current
-      // region even after rounding of o + dlt (a bound of exactly 1/2 could
-      // round to x1 = 3/2 and shift a quadratic stencil one node further)
-      small = small && dlt < R(0.49) && dlt > R(-0.49);
-      R x1 = o[d] + dlt;
-      if (x1 < R(-1) || x1 >= R(2)) {  // cannot happen below the Courant limit
-        raise_flag(flg, PIC_FLAG_OVERSPEED);
-        x1 = x1 < R(-1) ? R(-1) : R(1.5);
+      R Ep[3], Bp[3];
+      gather<DIMS, ORDER, R>(acc, s.o, Ep, Bp);
+      bool small = false;
+      if (!push_move<DIMS, R>(P, s, Ep, Bp, sh, o1, vz, small, flg)) {
+        pa.cell[p] = -1;
+        valid = false;
+      } else if (!small) {
+        deferred[atomicAdd(&flg->ndefer, 1u)] = p;
+        valid = false;
       }
-      int s = x1 >= R(1) ? 1 : (x1 < R(0) ? -1 : 0);
-      R on = x1 - R(s);
-      if (on >= R(1)) {  // -tiny + 1 rounded up to 1
-        on = R(0);
-        s += 1;
-      }
-      sh[d] = s;
-      o1[d] = on;
-      int cn = c3[d] + s;
-      if (P.bc[d] == PIC_BC_PERIODIC) {
-        cn = wrap1(cn, P.n[d]);
-      } else if (cn < 0 || cn > P.n[d] - 2) {
-        absorbed = true;
-      }
-      c1[d] = cn;
     }
-    const R vz = u[2] * ig;
-    if (fast && small) {
-      LdsCurrent<DIMS, ORDER, R> sink{
-          s_j, ((l[2] - G::j_lo_z) * G::jx + (l[1] - G::j_lo)) * G::jx + (l[0] - G::j_lo), s_j};
-      deposit<DIMS, ORDER, R>(sink, P.jfac, o, sh, o1, q, vz);
-    } else {
-      GlobalCurrent<R> sink{F.J, c3[0], c3[1], c3[2], P.n[0], P.n[1], P.n[2],
-                            open0, open1, open2, DIMS, 0, 0, 0};
-      deposit<DIMS, ORDER, R>(sink, P.jfac, o, sh, o1, q, vz);
+    Split<DIMS, R> S;
+    S.m = 0;
+    const int pbase = ((l[2] - G::j_lo_z) * G::jx + (l[1] - G::j_lo)) * G::jx + (l[0] - G::j_lo);
+    if (valid) {
+      split_path<DIMS, ORDER, R>(S, s.o, sh, o1);
+      R xa[3], xb[3], ft;
+      int base[3];
+      segment_ends<DIMS, ORDER, R>(S, 0, xa, xb, base, ft);
+      LdsCurrent<DIMS, ORDER, R> sink{s_j, pbase, s_j};
+      sink.segment(base);
+      deposit_segment<DIMS, ORDER, R>(sink, P.jfac, xa, xb, s.q, s.q * vz * ft);
+      store_particle<DIMS, R>(pa, p, s, o1, new_cell<DIMS, R>(P, c3, sh));
     }
-    // store the new state
+    // segments after the first
+    const int nx = valid ? S.m : 0;
+    const unsigned long long b0 = __ballot(nx & 1), b1 = __ballot(nx & 2);
+    const int total = (int)(__popcll(b0) + 2 * __popcll(b1));
+    if (total == 0) continue;
+    if (Q::on && qn + total <= Q::CAP) {
+      const unsigned long long below = (1ull << lane) - 1ull;
+      int pos = qn + (int)(__popcll(b0 & below) + 2 * __popcll(b1 & below));
+      for (int sg = 1; sg <= nx; ++sg, ++pos) {
+        R xa[3], xb[3], ft;
+        int base[3];
+        segment_ends<DIMS, ORDER, R>(S, sg, xa, xb, base, ft);
+        q_idx[qb + pos] = pbase + (base[2] * G::jx + base[1]) * G::jx + base[0];
+        q_val[0][qb + pos] = s.q;
+        q_val[1][qb + pos] = s.q * vz * ft;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) pa.u[c][p] = u[c];
-#pragma unroll
-    for (int d = 0; d < DIMS; ++d) pa.off[d][p] = o1[d];
-    pa.cell[p] = absorbed ? -1 : c1[0] + P.n[0] * (c1[1] + P.n[1] * c1[2]);
-    const unsigned long long nslow = __popcll(__ballot(!fast));
-    if (nslow && (threadIdx.x & 63) == __ffsll(__ballot(!fast)) - 1)
-      atomicAdd(&flg->slowpath, nslow);
+        for (int d = 0; d < 3; ++d) {
+          q_val[2 + d][qb + pos] = xa[d];
+          q_val[5 + d][qb + pos] = xb[d];
+        }
+      }
+      qn += total;
+      while (qn >= 64) {  // one whole-wavefront round from the queue's end
+        __builtin_amdgcn_wave_barrier();
+        const int r = qb + qn - 64 + lane;
+        const R xa[3] = {q_val[2][r], q_val[3][r], q_val[4][r]};
+        const R xb[3] = {q_val[5][r], q_val[6][r], q_val[7][r]};
+        qsink.seg = s_j + q_idx[r];
+        deposit_segment<DIMS, ORDER, R>(qsink, P.jfac, xa, xb, q_val[0][r], q_val[1][r]);
+        __builtin_amdgcn_wave_barrier();
+        qn -= 64;
+      }
+    } else {  // queue full (or not available): deposit in place
+      LdsCurrent<DIMS, ORDER, R> sink{s_j, pbase, s_j};
+      for (int sg = 1; sg <= nx; ++sg) {
+        R xa[3], xb[3], ft;
+        int base[3];
+        segment_ends<DIMS, ORDER, R>(S, sg, xa, xb, base, ft);
+        sink.segment(base);
+        deposit_segment<DIMS, ORDER, R>(sink, P.jfac, xa, xb, s.q, s.q * vz * ft);
+      }
+    }
+  }
+  if (Q::on && qn > 0) {  // drain the queue
+    __builtin_amdgcn_wave_barrier();
+    if (lane < qn) {
+      const int r = qb + lane;
+      const R xa[3] = {q_val[2][r], q_val[3][r], q_val[4][r]};
+      const R xb[3] = {q_val[5][r], q_val[6][r], q_val[7][r]};
+      qsink.seg = s_j + q_idx[r];
+      deposit_segment<DIMS, ORDER, R>(qsink, P.jfac, xa, xb, q_val[0][r], q_val[1][r]);
+    }
   }
   __syncthreads();
 
@@ -589,20 +798,55 @@ __global__ void __launch_bounds__((Geo<DIMS, ORDER, R>::NT)) k_push_deposit(
     const int comp = idx / G::j_vol;
     const int r = idx - comp * G::j_vol;
     const int lx = r % G::jx, ly = (r / G::jx) % G::jx, lz = r / (G::jx * G::jx);
-    const int ix = axis_slot(ox + G::j_lo + lx, P.n[0], open0, comp == 0);
-    const int iy = axis_slot(oy + G::j_lo + ly, P.n[1], open1, comp == 1);
-    const int iz = DIMS == 3 ? axis_slot(oz + G::j_lo_z + lz, P.n[2], open2, comp == 2) : 0;
+    const int ix = axis_slot(org[0] + G::j_lo + lx, P.n[0], open0, comp == 0);
+    const int iy = axis_slot(org[1] + G::j_lo + ly, P.n[1], open1, comp == 1);
+    const int iz = DIMS == 3 ? axis_slot(org[2] + G::j_lo_z + lz, P.n[2], open2, comp == 2) : 0;
     if (ix < 0 || iy < 0 || iz < 0) continue;
     atomic_add(&F.J[comp][ix + P.n[0] * (iy + P.n[1] * iz)], v);
   }
 }
 
+// Global-memory kernel for the deferred particles: the same gather, push,
+// move and deposit with fields read from and currents added to global
+// memory.  The list length is read on the device.
+template <int DIMS, int ORDER, typename R>
+__global__ void __launch_bounds__(256) k_push_deferred(KParams<R> P, DParts<R> pa, DFields<R> F,
+                                                       const int* __restrict__ deferred,
+                                                       DevFlags* flg) {
+  const int nd = (int)flg->ndefer;
+  const int open0 = P.bc[0] == PIC_BC_OPEN, open1 = P.bc[1] == PIC_BC_OPEN;
+  const int open2 = DIMS == 3 && P.bc[2] == PIC_BC_OPEN;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < nd; t += gridDim.x * blockDim.x) {
+    const int p = deferred[t];
+    PState<R> s = load_particle<DIMS, R>(pa, p, P.q_const);
+    int c3[3];
+    if (!decode<DIMS, R>(P, s, c3, flg)) continue;
+    GlobalFields<R> acc{F.E, F.B, c3[0], c3[1], c3[2], P.n[0], P.n[1], P.n[2],
+                        open0, open1, open2, DIMS};
+    R Ep[3], Bp[3], o1[3], vz = R(0);
+    int sh[3];
+    bool small;
+    gather<DIMS, ORDER, R>(acc, s.o, Ep, Bp);
+    if (!push_move<DIMS, R>(P, s, Ep, Bp, sh, o1, vz, small, flg)) {
+      pa.cell[p] = -1;
+      continue;
+    }
+    GlobalCurrent<R> sink{F.J, c3[0], c3[1], c3[2], P.n[0], P.n[1], P.n[2],
+                          open0, open1, open2, DIMS, 0, 0, 0};
+    deposit<DIMS, ORDER, R>(sink, P.jfac, s.o, sh, o1, s.q, vz);
+    store_particle<DIMS, R>(pa, p, s, o1, new_cell<DIMS, R>(P, c3, sh));
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0 && nd > 0) atomicAdd(&flg->slowpath, (unsigned long long)nd);
+}
+
+// Zero J and the deferred-list length before a push.
 template <typename R>
-__global__ void k_fill3(R* a, R* b, R* c, long n, R v) {
+__global__ void k_push_prologue(R* a, R* b, R* c, long n, DevFlags* flg) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) flg->ndefer = 0u;
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
-    a[i] = v;
-    b[i] = v;
-    c[i] = v;
+    a[i] = R(0);
+    b[i] = R(0);
+    c[i] = R(0);
   }
 }
 
@@ -627,12 +871,15 @@ static int launch_pd(const pic_ctx* ctx, const pic_particles* p, const pic_field
     F.B[c] = (R*)f->B[c];
     F.J[c] = (R*)f->J[c];
   }
+  DevFlags* flg = (DevFlags*)(w + L.flags);
+  int* deferred = (int*)(w + L.tmp_cell);  // the sort's scratch is free during a push
   const long ncell = (long)P.n[0] * P.n[1] * P.n[2];
-  k_fill3<R><<<dim3((unsigned)((ncell + 255) / 256 < 4096 ? (ncell + 255) / 256 : 4096)), dim3(256), 0, s>>>(
-      F.J[0], F.J[1], F.J[2], ncell, R(0));
-  const int grid = 8 * P.per_xcd;
-  k_push_deposit<DIMS, ORDER, R><<<dim3(grid), dim3(G::NT), 0, s>>>(
-      P, pa, F, (const int*)(w + L.starts), (DevFlags*)(w + L.flags));
+  const long fb = (ncell + 255) / 256;
+  k_push_prologue<R><<<dim3((unsigned)(fb < 4096 ? fb : 4096)), dim3(256), 0, s>>>(
+      F.J[0], F.J[1], F.J[2], ncell, flg);
+  k_push_tile<DIMS, ORDER, R><<<dim3(8 * P.per_xcd), dim3(G::NT), 0, s>>>(
+      P, pa, F, (const int*)(w + L.starts), deferred, flg);
+  k_push_deferred<DIMS, ORDER, R><<<dim3(1024), dim3(256), 0, s>>>(P, pa, F, deferred, flg);
   return (int)hipGetLastError();
 }
 

@@ -51,10 +51,11 @@ struct Geo {
   // double for both forms (gfx950 issues LDS double atomic adds ~17x faster
   // than single-precision ones, and the in-tile sum gains precision)
   static constexpr size_t lds_bytes = sizeof(R) * 6 * (size_t)e_vol + sizeof(double) * 3 * (size_t)j_vol;
-  // threads per workgroup: 8 wavefronts per CU in either case (two
-  // workgroups when their LDS fits twice in 160 KB), which leaves each lane
-  // up to 256 VGPRs for the unrolled gather and deposit
-  static constexpr int NT = DIMS == 2 ? 256 : (lds_bytes <= 80 * 1024 ? 256 : 512);
+  // threads per workgroup: in 3D one workgroup fills a CU's LDS, so it
+  // brings all the wavefronts: 16 (4 per SIMD, <= 128 VGPRs) in FP32, 8 in
+  // FP64 whose gather and deposit need more registers; 2D tiles are small
+  // and several workgroups share a CU
+  static constexpr int NT = DIMS == 2 ? 256 : (sizeof(R) == 4 ? 1024 : 512);
 };
 
 // Unsigned division by a runtime divisor through a precomputed multiplier
@@ -113,8 +114,8 @@ struct DFields {
 // Sticky flags and counters at the head of the workspace.
 struct DevFlags {
   unsigned int flags;
-  unsigned int pad;
-  unsigned long long slowpath;
+  unsigned int ndefer;          // particles deferred to the global-memory kernel this push
+  unsigned long long slowpath;  // total deferred pushes since the last clear
   unsigned long long pad2[6];
 };
 
