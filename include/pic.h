@@ -167,6 +167,24 @@ int pic_diagnostics(pic_ctx* ctx, const pic_particles* p, const pic_fields* f,
                     const double* rho_prev, const double* gauss_ref, double* rho_out,
                     double* gauss_out, pic_diag* out, void* ws, void* stream);
 
+/* Transpose of pic_field_advance (hand-written adjoint; the advance is linear
+ * in E, B, J).  In: lam->E, lam->B = adjoints of E^{n+1}, B^{n+1}.  Out, in
+ * place: lam->E, lam->B = adjoints of E^n, B^n through the field advance alone,
+ * and lam->J (overwritten) = adjoint of J^{n+1/2}.  The Mur updates on open
+ * faces are transposed with the rest. */
+int pic_field_advance_adjoint(pic_ctx* ctx, pic_fields* lam, void* ws, void* stream);
+
+/* Transpose (vector-Jacobian product) of pic_push_deposit for one step, along
+ * the branch the forward takes.  state_n: the particles at step n (cell, off,
+ * u^{n-1/2}, q; any order, no sort needed); EB_n: E^n and B^n (J unused).
+ * lam_f->J: in, adjoint of J^{n+1/2}; lam_f->E, lam_f->B: the gather's
+ * contribution is ADDED (atomics).  lam_p->off[d] (cell units) and
+ * lam_p->u[c]: in, adjoints of x^{n+1} and u^{n+1/2}; out, adjoints of x^n and
+ * u^{n-1/2}, slot by slot with state_n (lam_p->cell, q, id are unused).
+ * Absorbed particles (cell = -1) are skipped. */
+int pic_push_deposit_adjoint(pic_ctx* ctx, const pic_particles* state_n, const pic_fields* EB_n,
+                             pic_fields* lam_f, pic_particles* lam_p, void* ws, void* stream);
+
 /* Read (and optionally clear) the sticky device flags and the slow-path
  * counter (synchronises `stream`).  Returns PIC_EDEVICE if any flag is set. */
 int pic_read_flags(pic_ctx* ctx, void* ws, int clear, uint32_t* flags, int64_t* n_slowpath,

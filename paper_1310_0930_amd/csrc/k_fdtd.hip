@@ -179,6 +179,15 @@ __global__ void k_mur(FdParams P, MurPlanes M, R* __restrict__ E0, R* __restrict
 }
 
 template <typename R>
+__global__ void k_fill3_zero(R* a, R* b, R* c, long n) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    a[i] = R(0);
+    b[i] = R(0);
+    c[i] = R(0);
+  }
+}
+
+template <typename R>
 static int launch_fa(const pic_ctx* ctx, const pic_fields* f, void* ws, hipStream_t s) {
   const pic_config& cf = ctx->cfg;
   FdParams P;
@@ -241,6 +250,222 @@ static int launch_fa(const pic_ctx* ctx, const pic_fields* f, void* ws, hipStrea
 int launch_field_advance(const pic_ctx* ctx, const pic_fields* f, void* ws, hipStream_t s) {
   return ctx->cfg.real_bytes == 8 ? launch_fa<double>(ctx, f, ws, s)
                                   : launch_fa<float>(ctx, f, ws, s);
+}
+
+// ------------------------------------------------------------------ adjoint
+// Transpose of the field advance (for the hand-written adjoint of the step).
+// The advance is linear in (E, B, J); with mu the adjoint of E^{n+1} after
+// the last half step, its transpose is, in reverse order:
+//   lamE -= h C^T mask(lamB)                      (the last half step)
+//   Mur updates transposed, edge pass then face pass
+//   lamB += dt C mu_interior;  lamJ = -dt mu_interior
+//   lamE = mu (+ the direct F1^n terms of Mur);   lamE -= h C^T mask(lamB)
+// where mask() keeps the B samples inside the domain (the only ones the
+// forward updates or reads) and mu_interior keeps the E samples advanced by
+// the Yee update.
+
+// lamE -= h C^T lamB over every E sample, lamB read only inside the domain.
+template <typename R>
+__global__ void k_adj_curl_b(FdParams P, R* __restrict__ L0, R* __restrict__ L1, R* __restrict__ L2,
+                             const R* __restrict__ B0, const R* __restrict__ B1,
+                             const R* __restrict__ B2, R gx, R gy, R gz, int ncell) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= ncell) return;
+  int i, j, k;
+  decompose(P, idx, i, j, k);
+  R* Lm[3] = {L0, L1, L2};
+  const R* B[3] = {B0, B1, B2};
+  const R g[3] = {gx, gy, gz};  // h / dx_d
+  auto bval = [&](int comp, int ii, int jj, int kk, int d, int step) -> R {
+    int Lc[3] = {ii, jj, kk};
+    Lc[d] += step;
+    if (Lc[d] < 0 || Lc[d] >= P.n[d]) {
+      if (P.open[d]) return R(0);
+      Lc[d] = Lc[d] < 0 ? Lc[d] + P.n[d] : Lc[d] - P.n[d];
+    }
+    if (!inside(P, Lc[0], Lc[1], Lc[2], comp != 0, comp != 1, comp != 2)) return R(0);
+    return B[comp][Lc[0] + P.n[0] * (Lc[1] + P.n[1] * Lc[2])];
+  };
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const int a = (c + 1) % 3, b = (c + 2) % 3;
+    R curl = R(0);
+    if (a < P.dims) curl += g[a] * (bval(b, i, j, k, a, 0) - bval(b, i, j, k, a, -1));
+    if (b < P.dims) curl -= g[b] * (bval(a, i, j, k, b, 0) - bval(a, i, j, k, b, -1));
+    Lm[c][idx] -= curl;
+  }
+}
+
+// Mur transpose for the samples of face (d, side) with `pass` open
+// boundary axes: mu[s1] += kappa mu[s0]; extra[s1] += mu[s0]; the sample's
+// own adjoint becomes -kappa mu[s0] (+ what it received as a neighbour,
+// kept in extra).  Runs for pass 2, then pass 1.
+template <typename R>
+__global__ void k_adj_mur(FdParams P, R* __restrict__ M0, R* __restrict__ M1, R* __restrict__ M2,
+                          R* __restrict__ X0, R* __restrict__ X1, R* __restrict__ X2, int d,
+                          int side, int pass, R kappa) {
+  const int a = d == 0 ? 1 : 0, b = d == 2 ? 1 : 2;
+  const int na = P.n[a], nbv = b < P.dims ? P.n[b] : 1;
+  const long plane = (long)na * nbv;
+  const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (t >= 2 * plane) return;
+  const int which = (int)(t / plane);
+  const long r = t - which * plane;
+  const int c = (d + 1 + which) % 3;
+  int L[3];
+  L[d] = side ? P.n[d] - 1 : 0;
+  L[a] = (int)(r % na);
+  L[b] = (int)(r / na);
+  if (!inside(P, L[0], L[1], L[2], c == 0, c == 1, c == 2)) return;
+  int lowest;
+  if (mur_axes(P, c, L[0], L[1], L[2], lowest) != pass || lowest != d) return;
+  R* M[3] = {M0, M1, M2};
+  R* X[3] = {X0, X1, X2};
+  const int i0 = L[0] + P.n[0] * (L[1] + P.n[1] * L[2]);
+  int N[3] = {L[0], L[1], L[2]};
+  N[d] += side ? -1 : 1;
+  const int i1 = N[0] + P.n[0] * (N[1] + P.n[1] * N[2]);
+  const R mu0 = M[c][i0];
+  M[c][i1] += kappa * mu0;
+  X[c][i1] += mu0;
+  M[c][i0] = -kappa * mu0 + X[c][i0];
+  X[c][i0] = R(0);
+}
+
+// lamB += dt C mu over the inside B samples, mu read on the E samples the
+// Yee update advances (interior ones).
+template <typename R>
+__global__ void k_adj_curl_e(FdParams P, const R* __restrict__ M0, const R* __restrict__ M1,
+                             const R* __restrict__ M2, R* __restrict__ B0, R* __restrict__ B1,
+                             R* __restrict__ B2, R gx, R gy, R gz, int ncell) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= ncell) return;
+  int i, j, k;
+  decompose(P, idx, i, j, k);
+  const R* M[3] = {M0, M1, M2};
+  R* B[3] = {B0, B1, B2};
+  const R g[3] = {gx, gy, gz};  // dt / dx_d
+  auto muval = [&](int comp, int ii, int jj, int kk, int d, int step) -> R {
+    int Lc[3] = {ii, jj, kk};
+    Lc[d] += step;
+    if (Lc[d] < 0 || Lc[d] >= P.n[d]) {
+      if (P.open[d]) return R(0);
+      Lc[d] = Lc[d] < 0 ? Lc[d] + P.n[d] : Lc[d] - P.n[d];
+    }
+    if (!inside(P, Lc[0], Lc[1], Lc[2], comp == 0, comp == 1, comp == 2)) return R(0);
+    int lowest;
+    if (mur_axes(P, comp, Lc[0], Lc[1], Lc[2], lowest) > 0) return R(0);
+    return M[comp][Lc[0] + P.n[0] * (Lc[1] + P.n[1] * Lc[2])];
+  };
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    if (!inside(P, i, j, k, c != 0, c != 1, c != 2)) continue;
+    const int a = (c + 1) % 3, b = (c + 2) % 3;
+    R acc = R(0);
+    if (a < P.dims) acc += g[a] * (muval(b, i, j, k, a, 1) - muval(b, i, j, k, a, 0));
+    if (b < P.dims) acc -= g[b] * (muval(a, i, j, k, b, 1) - muval(a, i, j, k, b, 0));
+    B[c][idx] += acc;
+  }
+}
+
+// lamJ = -dt mu on interior E samples (0 elsewhere); lamE = mu + extra there.
+template <typename R>
+__global__ void k_adj_e_out(FdParams P, R* __restrict__ M0, R* __restrict__ M1, R* __restrict__ M2,
+                            R* __restrict__ J0, R* __restrict__ J1, R* __restrict__ J2,
+                            R* __restrict__ X0, R* __restrict__ X1, R* __restrict__ X2, R dt,
+                            int ncell, int has_extra) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= ncell) return;
+  int i, j, k;
+  decompose(P, idx, i, j, k);
+  R* M[3] = {M0, M1, M2};
+  R* J[3] = {J0, J1, J2};
+  R* X[3] = {X0, X1, X2};
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    int lowest;
+    const bool yee = inside(P, i, j, k, c == 0, c == 1, c == 2) && mur_axes(P, c, i, j, k, lowest) == 0;
+    if (yee) {
+      J[c][idx] = -dt * M[c][idx];
+      if (has_extra) {
+        M[c][idx] += X[c][idx];
+        X[c][idx] = R(0);
+      }
+    } else {
+      J[c][idx] = R(0);
+    }
+  }
+}
+
+template <typename R>
+static int launch_fa_adj(const pic_ctx* ctx, const pic_fields* lam, void* ws, hipStream_t s) {
+  const pic_config& cf = ctx->cfg;
+  FdParams P;
+  P.dims = cf.dims;
+  bool any_open = false;
+  for (int d = 0; d < 3; ++d) {
+    P.n[d] = d < cf.dims ? cf.n[d] : 1;
+    P.open[d] = d < cf.dims && cf.bc[d] == PIC_BC_OPEN;
+    any_open = any_open || P.open[d];
+  }
+  P.dn0.init((uint32_t)P.n[0]);
+  P.dn1.init((uint32_t)P.n[1]);
+  const int ncell = P.n[0] * P.n[1] * P.n[2];
+  R h[3], g[3];
+  for (int d = 0; d < 3; ++d) {
+    h[d] = (R)(0.5 * cf.dt / cf.dx[d]);
+    g[d] = (R)(cf.dt / cf.dx[d]);
+  }
+  R* E[3];
+  R* B[3];
+  R* J[3];
+  for (int c = 0; c < 3; ++c) {
+    E[c] = (R*)lam->E[c];
+    B[c] = (R*)lam->B[c];
+    J[c] = (R*)lam->J[c];
+  }
+  WsLayout L = ws_layout(ctx, 0);
+  R* extra = (R*)((char*)ws + L.adj);
+  R* X[3] = {extra, extra + ncell, extra + 2 * (long)ncell};
+  const unsigned grid = (unsigned)((ncell + 255) / 256);
+  k_adj_curl_b<R><<<dim3(grid), dim3(256), 0, s>>>(P, E[0], E[1], E[2], B[0], B[1], B[2], h[0],
+                                                  h[1], h[2], ncell);
+  if (any_open) {
+    k_fill3_zero<R><<<dim3(grid < 4096 ? grid : 4096), dim3(256), 0, s>>>(X[0], X[1], X[2], ncell);
+    for (int pass = 2; pass >= 1; --pass)
+      for (int d = 0; d < cf.dims; ++d) {
+        if (!P.open[d]) continue;
+        const int a = d == 0 ? 1 : 0, b = d == 2 ? 1 : 2;
+        const long plane = (long)P.n[a] * P.n[b];
+        const R kappa = (R)((cf.dt - cf.dx[d]) / (cf.dt + cf.dx[d]));
+        for (int sd = 0; sd < 2; ++sd)
+          k_adj_mur<R><<<dim3((unsigned)((2 * plane + 255) / 256)), dim3(256), 0, s>>>(
+              P, E[0], E[1], E[2], X[0], X[1], X[2], d, sd, pass, kappa);
+      }
+  }
+  k_adj_curl_e<R><<<dim3(grid), dim3(256), 0, s>>>(P, E[0], E[1], E[2], B[0], B[1], B[2], g[0],
+                                                  g[1], g[2], ncell);
+  k_adj_e_out<R><<<dim3(grid), dim3(256), 0, s>>>(P, E[0], E[1], E[2], J[0], J[1], J[2], X[0],
+                                                 X[1], X[2], (R)cf.dt, ncell, any_open ? 1 : 0);
+  k_adj_curl_b<R><<<dim3(grid), dim3(256), 0, s>>>(P, E[0], E[1], E[2], B[0], B[1], B[2], h[0],
+                                                  h[1], h[2], ncell);
+  return (int)hipGetLastError();
+}
+
+int launch_field_advance_adjoint(const pic_ctx* ctx, const pic_fields* lam, void* ws, hipStream_t s) {
+  return ctx->cfg.real_bytes == 8 ? launch_fa_adj<double>(ctx, lam, ws, s)
+                                  : launch_fa_adj<float>(ctx, lam, ws, s);
+}
+
+// Size (in reals) of the adjoint's scratch (open axes only).
+long adj_len(const pic_config& cf) {
+  bool open = false;
+  long ncell = 1;
+  for (int d = 0; d < cf.dims; ++d) {
+    open = open || cf.bc[d] == PIC_BC_OPEN;
+    ncell *= cf.n[d];
+  }
+  return open ? 3 * ncell : 0;
 }
 
 // Size (in reals) of the Mur save buffer.

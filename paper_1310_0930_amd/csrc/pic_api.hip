@@ -12,6 +12,7 @@
 namespace pic {
 long mur_len(const pic_config& cf);
 long diag_len(const pic_config& cf);
+long adj_len(const pic_config& cf);
 
 static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
@@ -31,6 +32,9 @@ WsLayout ws_layout(const pic_ctx* ctx, int64_t np) {
   L.diag_len = (size_t)diag_len(ctx->cfg);
   L.diag = off;
   off = align256(off + sizeof(double) * L.diag_len);
+  L.adj_len = (size_t)adj_len(ctx->cfg);
+  L.adj = off;
+  off = align256(off + R * L.adj_len);
   const size_t n = np > 0 ? (size_t)np : 0;
   L.tmp_cell = off;
   off = align256(off + sizeof(int) * n);
@@ -261,6 +265,32 @@ int pic_step(pic_ctx* ctx, pic_particles* p, pic_fields* f, int32_t nsteps, void
     ctx->steps_done += 1;
   }
   return PIC_OK;
+}
+
+int pic_field_advance_adjoint(pic_ctx* ctx, pic_fields* lam, void* ws, void* stream) {
+  if (!ctx || !ws) return PIC_EINVAL;
+  int v = check_fields(lam, true);
+  if (v) return v;
+  if ((v = ensure_device(ctx))) return v;
+  return hip_status(launch_field_advance_adjoint(ctx, lam, ws, (hipStream_t)stream));
+}
+
+int pic_push_deposit_adjoint(pic_ctx* ctx, const pic_particles* state_n, const pic_fields* EB_n,
+                             pic_fields* lam_f, pic_particles* lam_p, void* ws, void* stream) {
+  if (!ctx || !ws || !lam_p) return PIC_EINVAL;
+  int v = check_particles(ctx, state_n);
+  if (v) return v;
+  if ((v = check_fields(EB_n, false))) return v;
+  if ((v = check_fields(lam_f, true))) return v;
+  if (state_n->np > 0) {
+    for (int d = 0; d < ctx->cfg.dims; ++d)
+      if (!lam_p->off[d]) return PIC_EINVAL;
+    for (int c = 0; c < 3; ++c)
+      if (!lam_p->u[c]) return PIC_EINVAL;
+  }
+  if ((v = ensure_device(ctx))) return v;
+  return hip_status(
+      launch_push_deposit_adjoint(ctx, state_n, EB_n, lam_f, lam_p, ws, (hipStream_t)stream));
 }
 
 int pic_deposit_rho(pic_ctx* ctx, const pic_particles* p, double* rho, void* ws, void* stream) {

@@ -129,9 +129,11 @@ struct WsLayout {
   size_t tmp_id;     // int32[np]
   size_t mur;        // R[mur_len]  saved E planes next to open faces
   size_t diag;       // double[diag_len]  reduction partials
+  size_t adj;        // R[adj_len]  adjoint scratch (open axes)
   size_t total;
   size_t mur_len;
   size_t diag_len;
+  size_t adj_len;
 };
 
 }  // namespace pic
@@ -159,6 +161,10 @@ int launch_sort(const pic_ctx* ctx, const pic_particles* p, void* ws, hipStream_
 int launch_push_deposit(const pic_ctx* ctx, const pic_particles* p, const pic_fields* f,
                         void* ws, hipStream_t s);
 int launch_field_advance(const pic_ctx* ctx, const pic_fields* f, void* ws, hipStream_t s);
+int launch_field_advance_adjoint(const pic_ctx* ctx, const pic_fields* lam, void* ws, hipStream_t s);
+int launch_push_deposit_adjoint(const pic_ctx* ctx, const pic_particles* p, const pic_fields* f,
+                                const pic_fields* lam_f, pic_particles* lam_p, void* ws,
+                                hipStream_t s);
 int launch_deposit_rho(const pic_ctx* ctx, const pic_particles* p, double* rho, void* ws,
                        hipStream_t s);
 int launch_diagnostics(const pic_ctx* ctx, const pic_particles* p, const pic_fields* f,

@@ -75,6 +75,11 @@ _SIGS = {
     "pic_diagnostics": ([C.c_void_p, C.POINTER(PicParticles), C.POINTER(PicFields), C.c_void_p,
                          C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(PicDiag), C.c_void_p,
                          C.c_void_p], C.c_int),
+    "pic_field_advance_adjoint": ([C.c_void_p, C.POINTER(PicFields), C.c_void_p, C.c_void_p],
+                                  C.c_int),
+    "pic_push_deposit_adjoint": ([C.c_void_p, C.POINTER(PicParticles), C.POINTER(PicFields),
+                                  C.POINTER(PicFields), C.POINTER(PicParticles), C.c_void_p,
+                                  C.c_void_p], C.c_int),
     "pic_read_flags": ([C.c_void_p, C.c_void_p, C.c_int, C.POINTER(C.c_uint32),
                         C.POINTER(C.c_int64), C.c_void_p], C.c_int),
     "pic_strerror": ([C.c_int], C.c_char_p),
@@ -171,6 +176,35 @@ def pic_diagnostics(ctx, parts, fields, rho_prev, gauss_ref, rho_out, gauss_out,
                                  C.c_void_p(gauss_out or 0), C.byref(d), C.c_void_p(ws),
                                  _stream(stream)), "pic_diagnostics")
     return d
+
+
+def pic_field_advance_adjoint(ctx, lam_fields: PicFields, ws, stream=None):
+    _check(lib().pic_field_advance_adjoint(ctx, C.byref(lam_fields), C.c_void_p(ws), _stream(stream)),
+           "pic_field_advance_adjoint")
+
+
+def pic_push_deposit_adjoint(ctx, parts: PicParticles, fields: PicFields, lam_fields: PicFields,
+                             lam_parts: PicParticles, ws, stream=None):
+    _check(lib().pic_push_deposit_adjoint(ctx, C.byref(parts), C.byref(fields), C.byref(lam_fields),
+                                          C.byref(lam_parts), C.c_void_p(ws), _stream(stream)),
+           "pic_push_deposit_adjoint")
+
+
+def fields_struct(E, B, J=None) -> PicFields:
+    """PicFields over (3, ncell) device tensors."""
+    nul = (C.c_void_p * 3)(None, None, None)
+    return PicFields((C.c_void_p * 3)(*[E[c].data_ptr() for c in range(3)]),
+                     (C.c_void_p * 3)(*[B[c].data_ptr() for c in range(3)]),
+                     nul if J is None else (C.c_void_p * 3)(*[J[c].data_ptr() for c in range(3)]))
+
+
+def particles_struct(np_, cell, off, u, q=None, id_=None) -> PicParticles:
+    """PicParticles over SoA device tensors (off and u are (3, np))."""
+    return PicParticles(
+        int(np_), None if cell is None else cell.data_ptr(),
+        (C.c_void_p * 3)(*[off[d].data_ptr() for d in range(3)]),
+        (C.c_void_p * 3)(*[u[c].data_ptr() for c in range(3)]),
+        None if q is None else q.data_ptr(), None if id_ is None else id_.data_ptr())
 
 
 def pic_read_flags(ctx, ws, clear=False, stream=None):
