@@ -23,6 +23,19 @@ __device__ __forceinline__ int axis_slot(int i, int n, int open, int st) {
   return (i < 0 || i > n - 1 - st) ? -1 : i;
 }
 
+// Storage offsets along one axis of the sample at lattice index i, for a
+// node-located (s[0]) and a staggered (s[1]) quantity, already multiplied
+// by the axis stride; -1 outside the domain of an open axis.  Region loops
+// form them once per sample and share them over the field components.
+__device__ __forceinline__ void axis_slots(int i, int n, int open, int stride, int* s) {
+  if (!open) {
+    s[0] = s[1] = axis_slot(i, n, 0, 0) * stride;
+    return;
+  }
+  s[0] = (i < 0 || i > n - 1) ? -1 : i * stride;
+  s[1] = (i < 0 || i > n - 2) ? -1 : i * stride;
+}
+
 template <typename R>
 __device__ __forceinline__ void atomic_add(R* p, R v) {
   atomicAdd(p, v);

@@ -133,7 +133,8 @@ struct GlobalFields {
 
 // Current sinks.  segment() fixes the first stencil node of a virtual
 // segment; add() then takes compile-time offsets from it.  The LDS tile
-// accumulates in double (see Geo); the global sink is the path of
+// accumulates in double, or (single form) in 64-bit integers of values the
+// caller has already scaled (see Geo); the global sink is the path of
 // particles off their tile.
 template <int DIMS, int ORDER, typename R>
 struct LdsCurrent {
@@ -145,7 +146,11 @@ struct LdsCurrent {
     seg = s + base + (b[2] * G::jx + b[1]) * G::jx + b[0];
   }
   __device__ __forceinline__ void add(int comp, int i, int j, int k, R v) const {
-    atomicAdd(&seg[comp * G::j_vol + (k * G::jx + j) * G::jx + i], (double)v);
+    double* a = &seg[comp * G::j_vol + (k * G::jx + j) * G::jx + i];
+    if constexpr (G::fixed)
+      atomicAdd((unsigned long long*)a, (unsigned long long)(long long)__float2int_rn(v));
+    else
+      atomicAdd(a, (double)v);
   }
 };
 

@@ -69,38 +69,73 @@ __global__ void __launch_bounds__((Geo<DIMS, ORDER, R>::NT)) k_push_tile(
   const int open0 = P.bc[0] == PIC_BC_OPEN, open1 = P.bc[1] == PIC_BC_OPEN;
   const int open2 = DIMS == 3 && P.bc[2] == PIC_BC_OPEN;
 
-  // stage E and B of tile + halo (zero outside open faces); every load of a
-  // thread is issued before the first LDS store so that their latencies
-  // overlap
-  constexpr int NSTAGE = (6 * G::e_vol + G::NT - 1) / G::NT;
-  R stage[NSTAGE];
+  // stage E and B of tile + halo (zero outside open faces).  Each thread
+  // takes region samples and loads the six components there, with the
+  // storage offsets along each axis formed once per sample; every load is
+  // issued before the first LDS store so that their latencies overlap.
+  constexpr int NR = (G::e_vol + G::NT - 1) / G::NT;
+  const int str1 = P.n[0], str2 = P.n[0] * P.n[1];
+  R stage[NR][6];
 #pragma unroll
-  for (int k = 0; k < NSTAGE; ++k) {
-    const int idx = threadIdx.x + k * G::NT;
-    stage[k] = R(0);
-    if (idx < 6 * G::e_vol) {
-      const int comp = idx / G::e_vol;
-      const int r = idx - comp * G::e_vol;
+  for (int k = 0; k < NR; ++k) {
+    const int r = threadIdx.x + k * G::NT;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) stage[k][c] = R(0);
+    if (r < G::e_vol) {
       const int lx = r % G::ex, ly = (r / G::ex) % G::ex, lz = r / (G::ex * G::ex);
-      const int c = comp < 3 ? comp : comp - 3;
-      const bool isb = comp >= 3;
-      const int ix = axis_slot(org[0] + G::e_lo + lx, P.n[0], open0, isb ? (c != 0) : (c == 0));
-      const int iy = axis_slot(org[1] + G::e_lo + ly, P.n[1], open1, isb ? (c != 1) : (c == 1));
-      const int iz = DIMS == 3 ? axis_slot(org[2] + G::e_lo_z + lz, P.n[2], open2,
-                                           isb ? (c != 2) : (c == 2))
-                               : 0;
-      if (ix >= 0 && iy >= 0 && iz >= 0) {
-        const R* f = isb ? F.B[c] : F.E[c];
-        stage[k] = f[ix + P.n[0] * (iy + P.n[1] * iz)];
+      int sx[2], sy[2], sz[2] = {0, 0};
+      axis_slots(org[0] + G::e_lo + lx, P.n[0], open0, 1, sx);
+      axis_slots(org[1] + G::e_lo + ly, P.n[1], open1, str1, sy);
+      if (DIMS == 3) axis_slots(org[2] + G::e_lo_z + lz, P.n[2], open2, str2, sz);
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {  // E_c staggered along c, B_c along the two others
+        const int e = c < 3 ? c : c - 3;
+        const bool isb = c >= 3;
+        const int ix = sx[isb ? (e != 0) : (e == 0)];
+        const int iy = sy[isb ? (e != 1) : (e == 1)];
+        const int iz = sz[isb ? (e != 2) : (e == 2)];
+        if (ix >= 0 && iy >= 0 && iz >= 0) stage[k][c] = (isb ? F.B[e] : F.E[e])[ix + iy + iz];
       }
     }
   }
 #pragma unroll
-  for (int k = 0; k < NSTAGE; ++k) {
-    const int idx = threadIdx.x + k * G::NT;
-    if (idx < 6 * G::e_vol) s_eb[idx] = stage[k];
+  for (int k = 0; k < NR; ++k) {
+    const int r = threadIdx.x + k * G::NT;
+    if (r < G::e_vol) {
+#pragma unroll
+      for (int c = 0; c < 6; ++c) s_eb[c * G::e_vol + r] = stage[k][c];
+    }
   }
   for (int idx = threadIdx.x; idx < 3 * G::j_vol; idx += G::NT) s_j[idx] = 0.0;
+
+  // Scales of the fixed-point current tile (single form).  A contribution
+  // to J_c is q jfac_c P A with |P| <= |move along c| < 1/2 and 0 <= A <= 1
+  // (P is a difference of the cumulative shape, A an average of products
+  // of weights), so |contribution| < qmax |jfac_c| / 2; in 2D J_z is
+  // q v_z f A with |v_z| < 1, f <= 1, so qmax bounds it.  Scaling by 2^K
+  // with bound * 2^K <= 2^29 leaves each contribution a 32-bit integer
+  // (rounded to nearest, resolution ~1e-9 of the bound) and the 64-bit
+  // tile sums exact.  A particle whose |q| exceeds the bound the sort
+  // recorded (charges changed since) takes the global-memory path.
+  R jf[3] = {P.jfac[0], P.jfac[1], P.jfac[2]};
+  R zs = R(1);
+  double unscale[3] = {1.0, 1.0, 1.0};
+  const float qmax = pa.q ? __uint_as_float(flg->qmax) : fabsf((float)P.q_const);
+  const bool qmax_ok = qmax <= 3.0e38f;
+  if constexpr (G::fixed) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const bool z2 = DIMS == 2 && c == 2;
+      int e = 0;
+      frexpf(z2 ? qmax : qmax * fabsf((float)P.jfac[c]) * 0.5f, &e);  // bound < 2^e
+      const int K = qmax_ok ? 29 - e : 0;
+      if (z2)
+        zs = ldexpf(1.0f, K);
+      else
+        jf[c] = ldexpf((float)P.jfac[c], K);
+      unscale[c] = ldexp(1.0, -K);
+    }
+  }
   __syncthreads();
 
   const int lane = threadIdx.x & 63;
@@ -137,6 +172,7 @@ __global__ void __launch_bounds__((Geo<DIMS, ORDER, R>::NT)) k_push_tile(
     }
     R o1[3] = {R(0), R(0), R(0)}, vz = R(0);
     int sh[3] = {0, 0, 0};
+    if (G::fixed && pa.q && !(fabs(s.q) <= qmax && qmax_ok)) fast = false;
     if (valid && !fast) {  // leave the state as it was; the global-memory kernel redoes it
       deferred[atomicAdd(&flg->ndefer, 1u)] = p;
       valid = false;
@@ -165,7 +201,7 @@ __global__ void __launch_bounds__((Geo<DIMS, ORDER, R>::NT)) k_push_tile(
       segment_ends<DIMS, ORDER, R>(S, 0, xa, xb, base, ft);
       LdsCurrent<DIMS, ORDER, R> sink{s_j, pbase, s_j};
       sink.segment(base);
-      deposit_segment<DIMS, ORDER, R>(sink, P.jfac, xa, xb, s.q, s.q * vz * ft);
+      deposit_segment<DIMS, ORDER, R>(sink, jf, xa, xb, s.q, s.q * vz * ft * zs);
       store_particle<DIMS, R>(pa, p, s, o1, new_cell<DIMS, R>(P, c3, sh));
     }
     // segments after the first
@@ -182,7 +218,7 @@ __global__ void __launch_bounds__((Geo<DIMS, ORDER, R>::NT)) k_push_tile(
         segment_ends<DIMS, ORDER, R>(S, sg, xa, xb, base, ft);
         q_idx[qb + pos] = pbase + (base[2] * G::jx + base[1]) * G::jx + base[0];
         q_val[0][qb + pos] = s.q;
-        q_val[1][qb + pos] = s.q * vz * ft;
+        q_val[1][qb + pos] = s.q * vz * ft * zs;
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
           q_val[2 + d][qb + pos] = xa[d];
@@ -196,7 +232,7 @@ __global__ void __launch_bounds__((Geo<DIMS, ORDER, R>::NT)) k_push_tile(
         const R xa[3] = {q_val[2][r], q_val[3][r], q_val[4][r]};
         const R xb[3] = {q_val[5][r], q_val[6][r], q_val[7][r]};
         qsink.seg = s_j + q_idx[r];
-        deposit_segment<DIMS, ORDER, R>(qsink, P.jfac, xa, xb, q_val[0][r], q_val[1][r]);
+        deposit_segment<DIMS, ORDER, R>(qsink, jf, xa, xb, q_val[0][r], q_val[1][r]);
         __builtin_amdgcn_wave_barrier();
         qn -= 64;
       }
@@ -207,7 +243,7 @@ __global__ void __launch_bounds__((Geo<DIMS, ORDER, R>::NT)) k_push_tile(
         int base[3];
         segment_ends<DIMS, ORDER, R>(S, sg, xa, xb, base, ft);
         sink.segment(base);
-        deposit_segment<DIMS, ORDER, R>(sink, P.jfac, xa, xb, s.q, s.q * vz * ft);
+        deposit_segment<DIMS, ORDER, R>(sink, jf, xa, xb, s.q, s.q * vz * ft * zs);
       }
     }
   }
@@ -218,23 +254,28 @@ __global__ void __launch_bounds__((Geo<DIMS, ORDER, R>::NT)) k_push_tile(
       const R xa[3] = {q_val[2][r], q_val[3][r], q_val[4][r]};
       const R xb[3] = {q_val[5][r], q_val[6][r], q_val[7][r]};
       qsink.seg = s_j + q_idx[r];
-      deposit_segment<DIMS, ORDER, R>(qsink, P.jfac, xa, xb, q_val[0][r], q_val[1][r]);
+      deposit_segment<DIMS, ORDER, R>(qsink, jf, xa, xb, q_val[0][r], q_val[1][r]);
     }
   }
   __syncthreads();
 
   // flush the LDS current tile (its halo overlaps the neighbouring tiles')
-  for (int idx = threadIdx.x; idx < 3 * G::j_vol; idx += G::NT) {
-    const R v = (R)s_j[idx];
-    if (v == R(0)) continue;
-    const int comp = idx / G::j_vol;
-    const int r = idx - comp * G::j_vol;
+  for (int r = threadIdx.x; r < G::j_vol; r += G::NT) {
     const int lx = r % G::jx, ly = (r / G::jx) % G::jx, lz = r / (G::jx * G::jx);
-    const int ix = axis_slot(org[0] + G::j_lo + lx, P.n[0], open0, comp == 0);
-    const int iy = axis_slot(org[1] + G::j_lo + ly, P.n[1], open1, comp == 1);
-    const int iz = DIMS == 3 ? axis_slot(org[2] + G::j_lo_z + lz, P.n[2], open2, comp == 2) : 0;
-    if (ix < 0 || iy < 0 || iz < 0) continue;
-    atomic_add(&F.J[comp][ix + P.n[0] * (iy + P.n[1] * iz)], v);
+    int sx[2], sy[2], sz[2] = {0, 0};
+    axis_slots(org[0] + G::j_lo + lx, P.n[0], open0, 1, sx);
+    axis_slots(org[1] + G::j_lo + ly, P.n[1], open1, str1, sy);
+    if (DIMS == 3) axis_slots(org[2] + G::j_lo_z + lz, P.n[2], open2, str2, sz);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {  // J_c staggered along c
+      R v;
+      if constexpr (G::fixed)
+        v = (R)((double)((const long long*)s_j)[c * G::j_vol + r] * unscale[c]);
+      else
+        v = (R)s_j[c * G::j_vol + r];
+      const int ix = sx[c == 0], iy = sy[c == 1], iz = sz[c == 2];
+      if (v != R(0) && ix >= 0 && iy >= 0 && iz >= 0) atomic_add(&F.J[c][ix + iy + iz], v);
+    }
   }
 }
 

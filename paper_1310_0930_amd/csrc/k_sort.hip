@@ -58,8 +58,9 @@ __device__ __forceinline__ void wave_runs(int key, int& head_lane, int& run_len)
 }
 
 __global__ void k_sort_count(SortParams S, const int* __restrict__ cell, long np, int ncell,
-                             int* __restrict__ counts) {
+                             int* __restrict__ counts, DevFlags* flg) {
   const long p = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (p == 0) flg->qmax = 0u;  // the scatter (next launch) takes the new maximum
   const int key = p < np ? tile_key(S, cell[p], ncell) : -1;
   int head, len;
   wave_runs(key, head, len);
@@ -110,7 +111,7 @@ struct SortArrays {
 
 template <typename R>
 __global__ void k_sort_scatter(SortParams S, SortArrays<R> A, long np, int ncell,
-                               int* __restrict__ cursor) {
+                               int* __restrict__ cursor, DevFlags* flg) {
   const long p = blockIdx.x * (long)blockDim.x + threadIdx.x;
   const int cl = p < np ? A.cell[p] : 0;
   const int key = p < np ? tile_key(S, cl, ncell) : -1;
@@ -120,13 +121,26 @@ __global__ void k_sort_scatter(SortParams S, SortArrays<R> A, long np, int ncell
   int base = 0;
   if (lane == head && key >= 0) base = atomicAdd(&cursor[key], len);
   base = __shfl(base, head, 64);
+  if (A.q) {
+    // largest |q| as a float bit pattern (non-negative floats order as
+    // unsigned integers), rounded up so that it bounds every |q| of type R
+    unsigned m = 0u;
+    if (p < np) {
+      const R qa = fabs(A.q[p]);
+      float f = (float)qa;
+      if ((R)f < qa) f = nextafterf(f, INFINITY);
+      m = __float_as_uint(f);
+    }
+    for (int o = 32; o > 0; o >>= 1) m = max(m, (unsigned)__shfl_xor((int)m, o, 64));
+    if (lane == 0) atomicMax(&flg->qmax, m);
+  }
   if (p >= np) return;
   const long dst = (long)base + (lane - head);
   A.t_cell[dst] = (cl >= 0 && cl < ncell) ? cl : -1;
   for (int d = 0; d < S.dims; ++d) A.t_off[d][dst] = A.off[d][p];
   for (int c = 0; c < 3; ++c) A.t_u[c][dst] = A.u[c][p];
-  if (A.q) A.t_q[dst] = A.q[p];
   if (A.id) A.t_id[dst] = A.id[p];
+  if (A.q) A.t_q[dst] = A.q[p];
 }
 
 template <typename R>
@@ -174,7 +188,8 @@ static int launch_sort_t(const pic_ctx* ctx, const pic_particles* p, void* ws, h
     return (int)hipGetLastError();
   }
   const unsigned grid = (unsigned)((np + 255) / 256);
-  k_sort_count<<<dim3(grid), dim3(256), 0, s>>>(S, p->cell, np, ncell, counts);
+  DevFlags* flg = (DevFlags*)(w + L.flags);
+  k_sort_count<<<dim3(grid), dim3(256), 0, s>>>(S, p->cell, np, ncell, counts, flg);
   k_sort_scan<<<dim3(1), dim3(1024), 0, s>>>(counts, starts, nb);
   SortArrays<R> A;
   A.cell = p->cell;
@@ -190,7 +205,7 @@ static int launch_sort_t(const pic_ctx* ctx, const pic_particles* p, void* ws, h
   A.id = p->id;
   A.t_cell = (int*)(w + L.tmp_cell);
   A.t_id = (int*)(w + L.tmp_id);
-  k_sort_scatter<R><<<dim3(grid), dim3(256), 0, s>>>(S, A, np, ncell, counts);
+  k_sort_scatter<R><<<dim3(grid), dim3(256), 0, s>>>(S, A, np, ncell, counts, flg);
   const unsigned g2 = grid < 8192 ? grid : 8192;
   k_sort_copyback<R><<<dim3(g2), dim3(256), 0, s>>>(A, np, c.dims);
   return (int)hipGetLastError();

@@ -1,6 +1,7 @@
 // C ABI of libpic: argument validation, workspace layout and dispatch.
 // Validation happens on the host before any HIP call, so configuration
 // errors are reported the same way with or without a device.
+#include <cstddef>
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
@@ -333,7 +334,8 @@ int pic_read_flags(pic_ctx* ctx, void* ws, int clear, uint32_t* flags, int64_t* 
   if (clear) {
     DevFlags z;
     memset(&z, 0, sizeof(z));
-    if (hipMemcpyAsync(ws, &z, sizeof(z), hipMemcpyHostToDevice, s) != hipSuccess) return PIC_EHIP;
+    if (hipMemcpyAsync(ws, &z, offsetof(DevFlags, qmax), hipMemcpyHostToDevice, s) != hipSuccess)
+      return PIC_EHIP;
     if (hipStreamSynchronize(s) != hipSuccess) return PIC_EHIP;
   }
   if (flags) *flags = h.flags;

@@ -47,9 +47,13 @@ struct Geo {
   static constexpr int j_lo = -A + Rc::d_lo;
   static constexpr int j_lo_z = DIMS == 3 ? j_lo : 0;
   static constexpr int j_vol = jx * jx * jz;
-  // E/B staged in the working precision; the current tile accumulates in
-  // double for both forms (gfx950 issues LDS double atomic adds ~17x faster
-  // than single-precision ones, and the in-tile sum gains precision)
+  // E/B staged in the working precision.  The current tile has 8-byte
+  // cells: in the double form it accumulates with LDS double atomic adds;
+  // in the single form each contribution is rounded to a 32-bit integer on
+  // a power-of-two scale and summed exactly with LDS 64-bit integer atomic
+  // adds (on gfx950 these issue ~1.7x faster than double adds at scattered
+  // addresses, and single-precision LDS atomic adds ~17x slower)
+  static constexpr bool fixed = sizeof(R) == 4;
   static constexpr size_t lds_bytes = sizeof(R) * 6 * (size_t)e_vol + sizeof(double) * 3 * (size_t)j_vol;
   // threads per workgroup: in 3D one workgroup fills a CU's LDS, so it
   // brings all the wavefronts: 16 (4 per SIMD, <= 128 VGPRs) in FP32, 8 in
@@ -116,7 +120,11 @@ struct DevFlags {
   unsigned int flags;
   unsigned int ndefer;          // particles deferred to the global-memory kernel this push
   unsigned long long slowpath;  // total deferred pushes since the last clear
-  unsigned long long pad2[6];
+  // Written by the sort (not cleared with the flags): bit pattern of the
+  // largest |q| (as float) over the per-particle charges it moved.
+  unsigned int qmax;
+  unsigned int pad1;
+  unsigned long long pad2[5];
 };
 
 // ------------------------------------------------------------------ workspace
