@@ -2,6 +2,8 @@
 // adjoint: B-spline pieces and weights, LDS/global accessors, gather, Boris,
 // move, trajectory split and the Esirkepov segment deposit.
 #pragma once
+#include <type_traits>
+
 #include "k_common.h"
 
 namespace pic {
@@ -87,16 +89,37 @@ __device__ __forceinline__ void dshape(R xa, R xb, R* d) {
 // particle's cell in region coordinates; ref() folds a component's first
 // stencil node into one index so that every stencil offset below is a
 // compile-time immediate of the LDS read.
+template <typename T>
+using lds_ptr = __attribute__((address_space(3))) T*;
+
 template <int DIMS, int ORDER, typename R>
 struct LdsFields {
   using G = Geo<DIMS, ORDER, R>;
-  const R* s;
+  lds_ptr<const R> s;
   int base;
-  __device__ __forceinline__ const R* ref(int comp, const int* b) const {
-    return s + comp * G::e_vol + base + (b[2] * G::ex + b[1]) * G::ex + b[0];
+  __device__ __forceinline__ lds_ptr<const R> ref(int comp, const int* b) const {
+    // the component's first stencil node as one register, so that every
+    // stencil read is a small immediate from it (paired LDS reads reach 255
+    // elements; left to itself the compiler folds the array and component
+    // offsets into the immediates and then needs an address add per pair)
+    return pin(s + comp * G::e_vol + base + (b[2] * G::ex + b[1]) * G::ex + b[0]);
   }
-  __device__ __forceinline__ R at(const R* r, int /*comp*/, int i, int j, int k) const {
-    return r[(k * G::ex + j) * G::ex + i];
+  // planes 0 and 1 of the stencil are within reach of the first node's
+  // register; planes 2 and 3 get a second register (far)
+  __device__ __forceinline__ lds_ptr<const R> far(lds_ptr<const R> r) const {
+    return DIMS == 3 && ORDER >= 2 ? pin(r + 2 * G::ex * G::ex) : r;
+  }
+  __device__ __forceinline__ lds_ptr<const R> plane(lds_ptr<const R> r, lds_ptr<const R> r2,
+                                                    int k) const {
+    return k < 2 ? r + k * G::ex * G::ex : r2 + (k - 2) * G::ex * G::ex;
+  }
+  __device__ __forceinline__ R at(lds_ptr<const R> rk, int /*comp*/, int i, int j, int /*k*/) const {
+    return rk[j * G::ex + i];
+  }
+  static __device__ __forceinline__ lds_ptr<const R> pin(lds_ptr<const R> p) {
+    uint32_t a = (uint32_t)(uintptr_t)p;
+    asm volatile("" : "+v"(a));
+    return (lds_ptr<const R>)(uintptr_t)a;
   }
 };
 
@@ -116,6 +139,8 @@ struct GlobalFields {
   __device__ __forceinline__ Ref ref(int /*comp*/, const int* b) const {
     return {cx + b[0], cy + b[1], cz + b[2]};
   }
+  __device__ __forceinline__ Ref far(const Ref& r) const { return r; }
+  __device__ __forceinline__ Ref plane(const Ref& r, const Ref&, int) const { return r; }
   __device__ __forceinline__ R at(const Ref& r, int comp, int i, int j, int k) const {
     const int c = comp < 3 ? comp : comp - 3;
     const bool isb = comp >= 3;
@@ -145,12 +170,22 @@ struct LdsCurrent {
   __device__ __forceinline__ void segment(const int* b) {
     seg = s + base + (b[2] * G::jx + b[1]) * G::jx + b[0];
   }
-  __device__ __forceinline__ void add(int comp, int i, int j, int k, R v) const {
-    double* a = &seg[comp * G::j_vol + (k * G::jx + j) * G::jx + i];
-    if constexpr (G::fixed)
-      atomicAdd((unsigned long long*)a, (unsigned long long)(long long)__float2int_rn(v));
-    else
-      atomicAdd(a, (double)v);
+  // arithmetic type of the contributions: double for the fixed-point tile
+  using C = typename std::conditional<G::fixed, double, R>::type;
+  // add the contribution f * a
+  __device__ __forceinline__ void put(int comp, int i, int j, int k, C f, C a) const {
+    double* t = &seg[comp * G::j_vol + (k * G::jx + j) * G::jx + i];
+    if constexpr (G::fixed) {
+      // |f a| < 2^51: adding 1.5 * 2^52 rounds the product to an integer
+      // held in the low mantissa bits (one rounding, fused), and
+      // subtracting the constant's bit pattern leaves that integer in two's
+      // complement (the constant's low word is zero)
+      const double y = fma(f, a, 6755399441055744.0);
+      atomicAdd((unsigned long long*)t,
+                (unsigned long long)(__double_as_longlong(y) - 0x4338000000000000LL));
+    } else {
+      atomicAdd(t, (double)(f * a));
+    }
   }
 };
 
@@ -167,7 +202,9 @@ struct GlobalCurrent {
     sy = cy + b[1];
     sz = cz + b[2];
   }
-  __device__ __forceinline__ void add(int comp, int i, int j, int k, R v) const {
+  using C = R;
+  __device__ __forceinline__ void put(int comp, int i, int j, int k, R f, R a) const {
+    const R v = f * a;
     const int ix = axis_slot(sx + i, n0, o0, comp == 0);
     const int iy = axis_slot(sy + j, n1, o1, comp == 1);
     const int iz = dims == 3 ? axis_slot(sz + k, n2, o2, comp == 2) : 0;
@@ -185,15 +222,17 @@ __device__ __forceinline__ R interp(const Acc& acc, int comp, const R (*w)[ORDER
   constexpr int M = ORDER + 1;
   constexpr int MZ = DIMS == 3 ? M : 1;
   const auto r = acc.ref(comp, b);
+  const auto r2 = acc.far(r);
   R s = R(0);
 #pragma unroll
   for (int k = 0; k < MZ; ++k) {
+    const auto rk = acc.plane(r, r2, k);
     R sy = R(0);
 #pragma unroll
     for (int j = 0; j < M; ++j) {
       R sx = R(0);
 #pragma unroll
-      for (int i = 0; i < M; ++i) sx += w[0][i] * acc.at(r, comp, i, j, k);
+      for (int i = 0; i < M; ++i) sx += w[0][i] * acc.at(rk, comp, i, j, k);
       sy += w[1][j] * sx;
     }
     s += (DIMS == 3 ? w[2][k] : R(1)) * sy;
@@ -374,11 +413,14 @@ __device__ __forceinline__ void segment_ends(const Split<DIMS, R>& S, int s, R* 
 }
 
 // Esirkepov current of one segment whose first stencil node the sink holds.
-// fz (2D only) = q v_z times the segment's time fraction.
+// fz (2D only) = q v_z times the segment's time fraction.  Weights and
+// transverse factors are formed in R; the final products run in the sink's
+// arithmetic type.
 template <int DIMS, int ORDER, typename R, class Sink>
 __device__ __forceinline__ void deposit_segment(const Sink& sk, const R* jfac, const R* xa,
                                                 const R* xb, R q, R fz) {
   constexpr int M = ORDER + 1;
+  using C = typename Sink::C;
   // mean weight Sm = S0 + dS/2 and dS/12: the Esirkepov transverse factor
   // S0a S0b + (dSa S0b + S0a dSb)/2 + dSa dSb/3 equals Sma Smb + dSa dSb/12
   R Sm[3][M], dS[3][M], d12[3][M];
@@ -397,25 +439,25 @@ __device__ __forceinline__ void deposit_segment(const Sink& sk, const R* jfac, c
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const int a = (c + 1) % 3, b = (c + 2) % 3;
-      R P[ORDER];
+      C P[ORDER];
       R run = R(0);
 #pragma unroll
       for (int i = 0; i < ORDER; ++i) {
         run += dS[c][i];
-        P[i] = q * jfac[c] * run;
+        P[i] = (C)(q * jfac[c] * run);
       }
 #pragma unroll
       for (int ib = 0; ib < M; ++ib)
 #pragma unroll
         for (int ia = 0; ia < M; ++ia) {
-          const R A = Sm[a][ia] * Sm[b][ib] + d12[a][ia] * dS[b][ib];
+          const C A = (C)(Sm[a][ia] * Sm[b][ib] + d12[a][ia] * dS[b][ib]);
 #pragma unroll
           for (int ic = 0; ic < ORDER; ++ic) {
             int L[3];
             L[c] = ic;
             L[a] = ia;
             L[b] = ib;
-            sk.add(c, L[0], L[1], L[2], P[ic] * A);
+            sk.put(c, L[0], L[1], L[2], P[ic], A);
           }
         }
     }
@@ -423,29 +465,31 @@ __device__ __forceinline__ void deposit_segment(const Sink& sk, const R* jfac, c
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
       const int a = 1 - c;
-      R P[ORDER];
+      C P[ORDER];
       R run = R(0);
 #pragma unroll
       for (int i = 0; i < ORDER; ++i) {
         run += dS[c][i];
-        P[i] = q * jfac[c] * run;
+        P[i] = (C)(q * jfac[c] * run);
       }
 #pragma unroll
       for (int ia = 0; ia < M; ++ia) {
+        const C A = (C)Sm[a][ia];
 #pragma unroll
         for (int ic = 0; ic < ORDER; ++ic) {
           int L[2];
           L[c] = ic;
           L[a] = ia;
-          sk.add(c, L[0], L[1], 0, P[ic] * Sm[a][ia]);
+          sk.put(c, L[0], L[1], 0, P[ic], A);
         }
       }
     }
+    const C fzc = (C)fz;
 #pragma unroll
     for (int j = 0; j < M; ++j)
 #pragma unroll
       for (int i = 0; i < M; ++i)
-        sk.add(2, i, j, 0, fz * (Sm[0][i] * Sm[1][j] + d12[0][i] * dS[1][j]));
+        sk.put(2, i, j, 0, fzc, (C)(Sm[0][i] * Sm[1][j] + d12[0][i] * dS[1][j]));
   }
 }
 

@@ -112,28 +112,35 @@ __global__ void __launch_bounds__((Geo<DIMS, ORDER, R>::NT)) k_push_tile(
   // to J_c is q jfac_c P A with |P| <= |move along c| < 1/2 and 0 <= A <= 1
   // (P is a difference of the cumulative shape, A an average of products
   // of weights), so |contribution| < qmax |jfac_c| / 2; in 2D J_z is
-  // q v_z f A with |v_z| < 1, f <= 1, so qmax bounds it.  Scaling by 2^K
-  // with bound * 2^K <= 2^29 leaves each contribution a 32-bit integer
-  // (rounded to nearest, resolution ~1e-9 of the bound) and the 64-bit
-  // tile sums exact.  A particle whose |q| exceeds the bound the sort
+  // q v_z f A with |v_z| < 1, f <= 1, so qmax bounds it.  A tile sample
+  // receives at most (DIMS+1) contributions per particle of the tile.  The
+  // power-of-two scale 2^K keeps every scaled contribution below 2^50 and
+  // every sum below 2^62, so contributions round to integers at ~2^-48 of
+  // the bound (single-precision values are kept exactly) and the 64-bit
+  // tile sums are exact.  A particle whose |q| exceeds the bound the sort
   // recorded (charges changed since) takes the global-memory path.
   R jf[3] = {P.jfac[0], P.jfac[1], P.jfac[2]};
   R zs = R(1);
-  double unscale[3] = {1.0, 1.0, 1.0};
+  int Ks[3] = {0, 0, 0};
   const float qmax = pa.q ? __uint_as_float(flg->qmax) : fabsf((float)P.q_const);
   const bool qmax_ok = qmax <= 3.0e38f;
   if constexpr (G::fixed) {
+    const unsigned ncontrib = (unsigned)(DIMS + 1) * (unsigned)(pend - pbeg);
+    const int g = 32 - __clz((int)(ncontrib - 1u));  // ncontrib <= 2^g
+    const int top = g > 12 ? 62 - g : 50;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const bool z2 = DIMS == 2 && c == 2;
       int e = 0;
       frexpf(z2 ? qmax : qmax * fabsf((float)P.jfac[c]) * 0.5f, &e);  // bound < 2^e
-      const int K = qmax_ok ? 29 - e : 0;
+      // uniform over the workgroup: keep the scales in scalar registers
+      Ks[c] = __builtin_amdgcn_readfirstlane(qmax_ok ? top - e : 0);
+      const float sc = ldexpf(z2 ? 1.0f : (float)P.jfac[c], Ks[c]);
+      const float su = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(sc)));
       if (z2)
-        zs = ldexpf(1.0f, K);
+        zs = su;
       else
-        jf[c] = ldexpf((float)P.jfac[c], K);
-      unscale[c] = ldexp(1.0, -K);
+        jf[c] = su;
     }
   }
   __syncthreads();
@@ -179,7 +186,7 @@ __global__ void __launch_bounds__((Geo<DIMS, ORDER, R>::NT)) k_push_tile(
     }
     if (valid) {
       LdsFields<DIMS, ORDER, R> acc{
-          s_eb, ((l[2] - G::e_lo_z) * G::ex + (l[1] - G::e_lo)) * G::ex + (l[0] - G::e_lo)};
+          (lds_ptr<const R>)s_eb, ((l[2] - G::e_lo_z) * G::ex + (l[1] - G::e_lo)) * G::ex + (l[0] - G::e_lo)};
       R Ep[3], Bp[3];
       gather<DIMS, ORDER, R>(acc, s.o, Ep, Bp);
       bool small = false;
@@ -270,7 +277,7 @@ __global__ void __launch_bounds__((Geo<DIMS, ORDER, R>::NT)) k_push_tile(
     for (int c = 0; c < 3; ++c) {  // J_c staggered along c
       R v;
       if constexpr (G::fixed)
-        v = (R)((double)((const long long*)s_j)[c * G::j_vol + r] * unscale[c]);
+        v = (R)ldexp((double)((const long long*)s_j)[c * G::j_vol + r], -Ks[c]);
       else
         v = (R)s_j[c * G::j_vol + r];
       const int ix = sx[c == 0], iy = sy[c == 1], iz = sz[c == 2];
