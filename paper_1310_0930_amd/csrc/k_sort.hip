@@ -1,18 +1,25 @@
-// Tile sort of the SoA particle arrays: counting sort on the tile of each
-// particle's cell (absorbed particles go to a last, dead bin).
+// Tile sort of the SoA particle arrays: counting sort on (tile of the
+// particle's cell, rank of the particle within its cell); absorbed
+// particles go to a last, dead bin.
 //
 // Not a step of the paper's method: it is the data layout that makes the
 // fused push/deposit local (one workgroup per tile, fields and currents in
 // LDS), the GPU counterpart of the paper's per-node particle partition
 // (Sec. 3) and of its answer to deposit write conflicts (Sec. 3.1, Sec. 5.2).
 //
-// Particles that share a tile are mostly contiguous already (they were
-// sorted before and drift slowly), so both the histogram and the scatter
-// aggregate runs of equal keys inside a wavefront: one global atomic per
-// run instead of one per particle, and each run keeps its order.
+// Inside a tile the particles come rank by rank: first one particle of
+// every cell, then a second one of every cell that has two, and so on, so a
+// wavefront's 64 lanes sit in different cells and their LDS accesses spread
+// over the banks.  Ranks come from per-cell counters (clamped to RB - 1).
+// Particles with equal keys are mostly contiguous already (they were
+// sorted before and drift slowly), so the rank counters, the histogram and
+// the scatter aggregate runs of equal values inside a wavefront: one global
+// atomic per run instead of one per particle.
 #include "k_common.h"
 
 namespace pic {
+
+constexpr int RB = SORT_RANKS;
 
 struct SortParams {
   int n[3];
@@ -57,42 +64,89 @@ __device__ __forceinline__ void wave_runs(int key, int& head_lane, int& run_len)
   run_len = next - head_lane;
 }
 
+// Rank within the cell (run-aggregated per-cell counters), bin key
+// tile * RB + min(rank, RB - 1), and the histogram of the keys.
 __global__ void k_sort_count(SortParams S, const int* __restrict__ cell, long np, int ncell,
+                             int* __restrict__ cellcnt, int* __restrict__ keys,
                              int* __restrict__ counts, DevFlags* flg) {
   const long p = blockIdx.x * (long)blockDim.x + threadIdx.x;
   if (p == 0) flg->qmax = 0u;  // the scatter (next launch) takes the new maximum
-  const int key = p < np ? tile_key(S, cell[p], ncell) : -1;
+  const int lane = threadIdx.x & 63;
+  const int cl = p < np ? cell[p] : -1;
+  const bool live = cl >= 0 && cl < ncell;
   int head, len;
+  wave_runs(live ? cl : -1 - (int)(p < np), head, len);
+  int rank = 0;
+  if (live && lane == head) rank = atomicAdd(&cellcnt[cl], len);
+  rank = __shfl(rank, head, 64) + (lane - head);
+  const int key = p >= np ? -1 : live ? tile_key(S, cl, ncell) * RB + min(rank, RB - 1) : S.ntiles * RB;
+  if (p < np) keys[p] = key;
   wave_runs(key, head, len);
-  if ((int)(threadIdx.x & 63) == head && key >= 0) atomicAdd(&counts[key], len);
+  if (lane == head && key >= 0) atomicAdd(&counts[key], len);
 }
 
-// Exclusive scan of counts[0..nb) into starts[0..nb] with one workgroup;
-// the cursors (counts) are reset to the starts for the scatter.
-__global__ void __launch_bounds__(1024) k_sort_scan(int* __restrict__ counts, int* __restrict__ starts, int nb) {
-  __shared__ int part[1024];
+// Exclusive scan of counts[0..nb) in three passes: per-block sums, a scan of
+// the block sums (one workgroup), and per-block scans with their offsets.
+// starts[i] = cursor[i] = sum of counts[0..i); starts[nb] = total.
+constexpr int SCAN_B = 1024;
+
+__device__ __forceinline__ int block_incl_scan(int v, int* sh) {
   const int t = threadIdx.x;
-  const int chunk = (nb + 1023) / 1024;
-  const int lo = t * chunk;
-  const int hi = min(lo + chunk, nb);
-  int s = 0;
-  for (int i = lo; i < hi; ++i) s += counts[i];
-  part[t] = s;
+  sh[t] = v;
   __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {
-    const int v = t >= off ? part[t - off] : 0;
+  for (int off = 1; off < SCAN_B; off <<= 1) {
+    const int a = t >= off ? sh[t - off] : 0;
     __syncthreads();
-    part[t] += v;
+    sh[t] += a;
     __syncthreads();
   }
-  int run = part[t] - s;  // exclusive prefix of this chunk
-  for (int i = lo; i < hi; ++i) {
-    const int c = counts[i];
-    starts[i] = run;
-    counts[i] = run;
-    run += c;
+  return sh[t];
+}
+
+__global__ void __launch_bounds__(SCAN_B) k_scan_sums(const int* __restrict__ counts, int nb,
+                                                      int* __restrict__ bsum) {
+  __shared__ int sh[SCAN_B];
+  const int i = blockIdx.x * SCAN_B + threadIdx.x;
+  const int v = i < nb ? counts[i] : 0;
+  const int incl = block_incl_scan(v, sh);
+  if (threadIdx.x == SCAN_B - 1) bsum[blockIdx.x] = incl;
+}
+
+// one workgroup: exclusive scan of the nblk block sums in place
+__global__ void __launch_bounds__(SCAN_B) k_scan_blocks(int* __restrict__ bsum, int nblk) {
+  __shared__ int sh[SCAN_B];
+  int carry = 0;
+  for (int base = 0; base < nblk; base += SCAN_B) {
+    const int i = base + threadIdx.x;
+    const int v = i < nblk ? bsum[i] : 0;
+    const int incl = block_incl_scan(v, sh);
+    if (i < nblk) bsum[i] = carry + incl - v;
+    carry += sh[SCAN_B - 1];
+    __syncthreads();
   }
-  if (t == 1023) starts[nb] = part[1023];
+}
+
+__global__ void __launch_bounds__(SCAN_B) k_scan_apply(int* __restrict__ counts, int nb,
+                                                       const int* __restrict__ bsum,
+                                                       int* __restrict__ starts) {
+  __shared__ int sh[SCAN_B];
+  const int i = blockIdx.x * SCAN_B + threadIdx.x;
+  const int v = i < nb ? counts[i] : 0;
+  const int incl = block_incl_scan(v, sh);
+  const int ex = bsum[blockIdx.x] + incl - v;
+  if (i < nb) {
+    starts[i] = ex;
+    counts[i] = ex;  // cursor for the scatter
+  }
+  if (i == nb - 1) starts[nb] = ex + v;
+}
+
+// Tile starts for the push: tstart[t] = first particle of tile t
+// (t = ntiles: first absorbed particle), tstart[ntiles + 1] = np.
+__global__ void k_tile_starts(const int* __restrict__ bstart, int ntiles, int* __restrict__ tstart) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t <= ntiles) tstart[t] = bstart[t * RB];
+  if (t == ntiles + 1) tstart[t] = bstart[ntiles * RB + 1];
 }
 
 template <typename R>
@@ -110,11 +164,12 @@ struct SortArrays {
 };
 
 template <typename R>
-__global__ void k_sort_scatter(SortParams S, SortArrays<R> A, long np, int ncell,
-                               int* __restrict__ cursor, DevFlags* flg) {
+__global__ void k_sort_scatter(SortArrays<R> A, long np, int ncell, int dims,
+                               const int* __restrict__ keys, int* __restrict__ cursor,
+                               DevFlags* flg) {
   const long p = blockIdx.x * (long)blockDim.x + threadIdx.x;
   const int cl = p < np ? A.cell[p] : 0;
-  const int key = p < np ? tile_key(S, cl, ncell) : -1;
+  const int key = p < np ? keys[p] : -1;
   int head, len;
   wave_runs(key, head, len);
   const int lane = threadIdx.x & 63;
@@ -137,7 +192,7 @@ __global__ void k_sort_scatter(SortParams S, SortArrays<R> A, long np, int ncell
   if (p >= np) return;
   const long dst = (long)base + (lane - head);
   A.t_cell[dst] = (cl >= 0 && cl < ncell) ? cl : -1;
-  for (int d = 0; d < S.dims; ++d) A.t_off[d][dst] = A.off[d][p];
+  for (int d = 0; d < dims; ++d) A.t_off[d][dst] = A.off[d][p];
   for (int c = 0; c < 3; ++c) A.t_u[c][dst] = A.u[c][p];
   if (A.id) A.t_id[dst] = A.id[p];
   if (A.q) A.t_q[dst] = A.q[p];
@@ -181,16 +236,26 @@ static int launch_sort_t(const pic_ctx* ctx, const pic_particles* p, void* ws, h
   char* w = (char*)ws;
   int* counts = (int*)(w + L.counts);
   int* starts = (int*)(w + L.starts);
-  const int nb = S.ntiles + 1;  // + dead bin
-  k_fill_int<<<dim3((nb + 255) / 256), dim3(256), 0, s>>>(counts, nb + 1, 0);
+  int* bstart = (int*)(w + L.bstart);
+  int* bsum = (int*)(w + L.bsum);
+  int* cellcnt = (int*)(w + L.cellcnt);
+  int* keys = (int*)(w + L.keys);
+  const int nb = S.ntiles * RB + 1;  // + dead bin
+  const int nblk = (nb + SCAN_B - 1) / SCAN_B;
   if (np == 0) {
-    k_fill_int<<<dim3((nb + 256) / 256), dim3(256), 0, s>>>(starts, nb + 1, 0);
+    k_fill_int<<<dim3((S.ntiles + 2 + 255) / 256), dim3(256), 0, s>>>(starts, S.ntiles + 2, 0);
     return (int)hipGetLastError();
   }
+  auto fill_grid = [](long n) { return dim3((unsigned)((n + 255) / 256 < 16384 ? (n + 255) / 256 : 16384)); };
+  k_fill_int<<<fill_grid(nb), dim3(256), 0, s>>>(counts, nb, 0);
+  k_fill_int<<<fill_grid(ncell), dim3(256), 0, s>>>(cellcnt, ncell, 0);
   const unsigned grid = (unsigned)((np + 255) / 256);
   DevFlags* flg = (DevFlags*)(w + L.flags);
-  k_sort_count<<<dim3(grid), dim3(256), 0, s>>>(S, p->cell, np, ncell, counts, flg);
-  k_sort_scan<<<dim3(1), dim3(1024), 0, s>>>(counts, starts, nb);
+  k_sort_count<<<dim3(grid), dim3(256), 0, s>>>(S, p->cell, np, ncell, cellcnt, keys, counts, flg);
+  k_scan_sums<<<dim3(nblk), dim3(SCAN_B), 0, s>>>(counts, nb, bsum);
+  k_scan_blocks<<<dim3(1), dim3(SCAN_B), 0, s>>>(bsum, nblk);
+  k_scan_apply<<<dim3(nblk), dim3(SCAN_B), 0, s>>>(counts, nb, bsum, bstart);
+  k_tile_starts<<<dim3((S.ntiles + 2 + 255) / 256), dim3(256), 0, s>>>(bstart, S.ntiles, starts);
   SortArrays<R> A;
   A.cell = p->cell;
   R* tr = (R*)(w + L.tmp_real);
@@ -205,7 +270,7 @@ static int launch_sort_t(const pic_ctx* ctx, const pic_particles* p, void* ws, h
   A.id = p->id;
   A.t_cell = (int*)(w + L.tmp_cell);
   A.t_id = (int*)(w + L.tmp_id);
-  k_sort_scatter<R><<<dim3(grid), dim3(256), 0, s>>>(S, A, np, ncell, counts, flg);
+  k_sort_scatter<R><<<dim3(grid), dim3(256), 0, s>>>(A, np, ncell, c.dims, keys, counts, flg);
   const unsigned g2 = grid < 8192 ? grid : 8192;
   k_sort_copyback<R><<<dim3(g2), dim3(256), 0, s>>>(A, np, c.dims);
   return (int)hipGetLastError();

@@ -23,10 +23,19 @@ WsLayout ws_layout(const pic_ctx* ctx, int64_t np) {
   size_t off = 0;
   L.flags = off;
   off = align256(off + sizeof(DevFlags));
-  L.counts = off;
-  off = align256(off + sizeof(int) * ((size_t)ctx->ntiles + 2));
+  const size_t nbins = (size_t)ctx->ntiles * SORT_RANKS + 1;
+  size_t ncell = 1;
+  for (int d = 0; d < ctx->cfg.dims; ++d) ncell *= (size_t)ctx->cfg.n[d];
   L.starts = off;
   off = align256(off + sizeof(int) * ((size_t)ctx->ntiles + 2));
+  L.counts = off;
+  off = align256(off + sizeof(int) * nbins);
+  L.bstart = off;
+  off = align256(off + sizeof(int) * (nbins + 1));
+  L.bsum = off;
+  off = align256(off + sizeof(int) * (nbins / 1024 + 1));
+  L.cellcnt = off;
+  off = align256(off + sizeof(int) * ncell);
   L.mur_len = (size_t)mur_len(ctx->cfg);
   L.mur = off;
   off = align256(off + R * L.mur_len);
@@ -40,6 +49,8 @@ WsLayout ws_layout(const pic_ctx* ctx, int64_t np) {
   L.tmp_cell = off;
   off = align256(off + sizeof(int) * n);
   L.tmp_id = off;
+  off = align256(off + sizeof(int) * n);
+  L.keys = off;
   off = align256(off + sizeof(int) * n);
   L.tmp_real = off;
   off = align256(off + R * 7 * n);

@@ -128,10 +128,18 @@ struct DevFlags {
 };
 
 // ------------------------------------------------------------------ workspace
+// The sort bins particles by (tile, rank within the cell), SORT_RANKS rank
+// buckets per tile, plus one dead bin.
+constexpr int SORT_RANKS = 16;
+
 struct WsLayout {
   size_t flags;      // DevFlags
-  size_t counts;     // int32[ntiles + 2]   per-tile counts / cursors
-  size_t starts;     // int32[ntiles + 2]   bin starts (ntiles + 1 used, last = dead bin end)
+  size_t starts;     // int32[ntiles + 2]   tile starts (entry ntiles = dead bin start, then np)
+  size_t counts;     // int32[nbins]        bin counts / scatter cursors
+  size_t bstart;     // int32[nbins + 1]    bin starts
+  size_t bsum;       // int32[nbins / 1024 + 1]  scan block sums
+  size_t cellcnt;    // int32[ncell]        particles per cell (ranks)
+  size_t keys;       // int32[np]           bin of each particle
   size_t tmp_cell;   // int32[np]
   size_t tmp_real;   // R[np * 7]  off[3], u[3], q
   size_t tmp_id;     // int32[np]

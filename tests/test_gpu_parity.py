@@ -227,7 +227,7 @@ def test_fdtd_eigenmode_fp64():
 
 
 # ---------------------------------------------------------------- edge cases
-def test_sort_groups_by_tile_and_keeps_a_permutation():
+def test_sort_groups_by_tile_and_rank_and_keeps_a_permutation():
     w = I.Workload("w3d_sort", 3, (40, 24, 16), (0.2, 0.2, 0.2), 2, 3, 0.3, 1,
                    seed=I.SEED_BASE + 70)
     pl, E, B = inputs_for(w)
@@ -248,6 +248,16 @@ def test_sort_groups_by_tile_and_keeps_a_permutation():
     tx, ty, tz = (c % 40) // T, (c // 40) % 24 // T, c // (40 * 24) // T
     key = tx + 5 * (ty + 3 * tz)
     assert np.all(np.diff(key) >= 0)
+    # inside a tile the particles come rank by rank: the k-th particle of
+    # every cell before any (k+1)-th one (ranks from 15 on share a bucket)
+    for t in np.unique(key):
+        cells = c[key == t]
+        seen = {}
+        rank = np.empty(cells.size, dtype=np.int64)
+        for i, cl in enumerate(cells):
+            rank[i] = seen.get(cl, 0)
+            seen[cl] = rank[i] + 1
+        assert np.all(np.diff(np.minimum(rank, 15)) >= 0), t
 
 
 def test_empty_and_ragged_particle_counts():
