@@ -337,7 +337,15 @@ __device__ __forceinline__ void split_path(Split<DIMS, R>& S, const R* o0, const
       const bool up = S.k1[d] > S.k0[d];
       S.pk0[d] = odd ? (up ? R(1) : R(0)) : (up ? R(0.5) : R(-0.5));
       S.pk1[d] = odd ? (up ? R(0) : R(1)) : (up ? R(-0.5) : R(0.5));
-      const R f = (S.pk0[d] - S.xi0[d]) / S.dl[d];
+      // crossing fraction; charge conservation does not depend on its last
+      // bits (neighbouring segments share their end points exactly), so
+      // single precision takes a reciprocal instead of a correctly rounded
+      // division
+      R f;
+      if constexpr (sizeof(R) == 4)
+        f = (S.pk0[d] - S.xi0[d]) * __builtin_amdgcn_rcpf(S.dl[d]);
+      else
+        f = (S.pk0[d] - S.xi0[d]) / S.dl[d];
       if (f > R(0) && f < R(1)) {
         S.cr[d] = true;
         fr[d] = f;
