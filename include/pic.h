@@ -84,7 +84,8 @@ typedef struct {
   int32_t sort_every; /* pic_step re-sorts every this many steps (>= 1) */
   int32_t drift;      /* cells a particle may drift out of its tile before it
                          takes the global-memory path; < 0 selects the default */
-  double q_over_m;    /* charge-to-mass ratio (-1 for electrons) */
+  double q_over_m;    /* charge-to-mass ratio of the species, in e/m_e (-1 for
+                         electrons, Z m_e/m_i for ions); one context per species */
   double q_const;     /* charge of every particle when pic_particles.q is NULL */
 } pic_config;
 
@@ -110,7 +111,8 @@ typedef struct {
   double cont_rel_l2;   /* ||C||_2 / ||(rho - rho_prev)/dt||_2 */
   double cont_rel_inf;  /* cont_max / (max|rho| / dt) */
   double w_field;       /* 1/2 sum (E^2 + B^2) dV over samples inside the domain */
-  double w_kin;         /* sum over live particles of |q_p| dV (gamma - 1) */
+  double w_kin;         /* sum over live particles of m_p dV (gamma - 1), with the
+                           mass density m_p = |q_p| / |q_over_m| (all species) */
   double rho_max;       /* max |rho| */
   int64_t n_alive;      /* particles with cell >= 0 */
   uint32_t flags;       /* sticky pic_flag bits */
@@ -153,9 +155,32 @@ int pic_field_advance(pic_ctx* ctx, pic_fields* f, void* ws, void* stream);
 int pic_step(pic_ctx* ctx, pic_particles* p, pic_fields* f, int32_t nsteps, void* ws,
              void* stream);
 
+/* Mobile ions and other extra species (the LWFA-1 run of Sec. 6 keeps the
+ * ions mobile; each species is pushed in the same E, B and the current of the
+ * loop of Sec. 2 is the sum of the species' currents).  One context per
+ * species (its q_over_m and q_const), with its own particle arrays and
+ * workspace, all contexts on the same grid, time step, order, precision and
+ * boundaries (PIC_EINVAL otherwise).
+ *
+ * pic_push_deposit_add: as pic_push_deposit but ADDS J^{n+1/2} of this
+ * species to f->J instead of overwriting it (same sort requirement). */
+int pic_push_deposit_add(pic_ctx* ctx, pic_particles* p, const pic_fields* f, void* ws,
+                         void* stream);
+
+/* `nsteps` full steps of `nspecies` species (arrays of that length): per step,
+ * every species is sorted when due (per context) and pushed (the first
+ * overwrites J, the others add to it), then the fields advance once (with
+ * ctx[0]'s workspace). */
+int pic_step_species(int32_t nspecies, pic_ctx* const* ctx, pic_particles* const* p,
+                     void* const* ws, pic_fields* f, int32_t nsteps, void* stream);
+
 /* FP64 charge density at the nodes from the stored cells and offsets with
  * order-n node shapes; `rho` holds n0*n1*n2 doubles and is overwritten. */
 int pic_deposit_rho(pic_ctx* ctx, const pic_particles* p, double* rho, void* ws, void* stream);
+
+/* Same, but adds this species' charge density to `rho` (several species). */
+int pic_deposit_rho_add(pic_ctx* ctx, const pic_particles* p, double* rho, void* ws,
+                        void* stream);
 
 /* FP64 diagnostics (synchronises `stream`): deposits rho^n into `rho_out`,
  * forms the Gauss residual D.E - rho^n (minus `gauss_ref` if not NULL; the
@@ -166,6 +191,14 @@ int pic_deposit_rho(pic_ctx* ctx, const pic_particles* p, double* rho, void* ws,
 int pic_diagnostics(pic_ctx* ctx, const pic_particles* p, const pic_fields* f,
                     const double* rho_prev, const double* gauss_ref, double* rho_out,
                     double* gauss_out, pic_diag* out, void* ws, void* stream);
+
+/* pic_diagnostics over several species sharing `f` (same conventions as
+ * pic_step_species): rho is the sum over species, w_kin and n_alive are
+ * summed, flags are or-ed and slow-path counts summed over the workspaces. */
+int pic_diagnostics_species(int32_t nspecies, pic_ctx* const* ctx, const pic_particles* const* p,
+                            void* const* ws, const pic_fields* f, const double* rho_prev,
+                            const double* gauss_ref, double* rho_out, double* gauss_out,
+                            pic_diag* out, void* stream);
 
 /* Transpose of pic_field_advance (hand-written adjoint; the advance is linear
  * in E, B, J).  In: lam->E, lam->B = adjoints of E^{n+1}, B^{n+1}.  Out, in

@@ -79,6 +79,7 @@ def lib():
             "oracle_boris": [cfgp, i64, P, P, P],
             "oracle_deposit_paths": [cfgp, i64, P, P, P, P, P],
             "oracle_push_deposit": [cfgp, i64, P, P, P, P, P, P, P, i32],
+            "oracle_push_deposit_add": [cfgp, i64, P, P, P, P, P, P, P, i32],
             "oracle_field_advance": [cfgp, P, P, P],
             "oracle_step": [cfgp, i64, P, P, P, P, P, P, P, i32, i32],
             "oracle_step_jvp": [cfgp, i64, P, P, P, P, P, P, P, P, P, P, P, P, i32],
@@ -212,6 +213,85 @@ class State:
                               _ptr(self.alive), _ptr(self.E), _ptr(self.B), C.byref(wf),
                               C.byref(wk))
         return wf.value, wk.value
+
+
+@dataclass
+class Species:
+    """One particle species of a multi-species state: its charge-to-mass
+    ratio, positions, momenta, charges and live flags (same conventions as
+    State)."""
+    q_over_m: float
+    X: np.ndarray
+    u: np.ndarray
+    q: np.ndarray
+    alive: np.ndarray = None
+
+    def __post_init__(self):
+        self.X = _f64(self.X, (-1, 3)).copy()
+        self.u = _f64(self.u, (-1, 3)).copy()
+        self.q = _f64(np.broadcast_to(self.q, (self.X.shape[0],))).copy()
+        if self.alive is None:
+            self.alive = np.ones(self.X.shape[0], dtype=np.int8)
+        self.alive = np.ascontiguousarray(self.alive, dtype=np.int8).copy()
+
+    @property
+    def np(self) -> int:
+        return self.X.shape[0]
+
+
+class MultiState:
+    """Several species in one set of fields (mobile ions, the LWFA-1 run of
+    Sec. 6).  A step zeroes J, pushes every species in E^n, B^n and adds its
+    current (each with its own q/m), then advances the fields once."""
+
+    def __init__(self, cfg: Config, species, E, B):
+        self.cfg = cfg
+        self.species = list(species)
+        self.E = _f64(E).reshape((3,) + cfg.shape).copy()
+        self.B = _f64(B).reshape((3,) + cfg.shape).copy()
+        self.J = cfg.zeros_field()
+
+    def _cfg(self, sp: Species) -> _Cfg:
+        c = self.cfg.c()
+        c.q_over_m = sp.q_over_m
+        return c
+
+    def push_deposit(self, nthreads: int = 1):
+        self.J[:] = 0.0
+        for sp in self.species:
+            lib().oracle_push_deposit_add(C.byref(self._cfg(sp)), sp.np, _ptr(sp.X), _ptr(sp.u),
+                                          _ptr(sp.q), _ptr(sp.alive), _ptr(self.E), _ptr(self.B),
+                                          _ptr(self.J), int(nthreads))
+
+    def field_advance(self):
+        lib().oracle_field_advance(C.byref(self.cfg.c()), _ptr(self.E), _ptr(self.B), _ptr(self.J))
+
+    def step(self, nsteps: int = 1, nthreads: int = 1):
+        for _ in range(nsteps):
+            self.push_deposit(nthreads)
+            self.field_advance()
+
+    def rho(self):
+        """Total charge density (sum over species)."""
+        out = np.zeros(self.cfg.shape, dtype=np.float64)
+        part = np.zeros_like(out)
+        for sp in self.species:
+            lib().oracle_deposit_rho(C.byref(self._cfg(sp)), sp.np, _ptr(sp.X), _ptr(sp.q),
+                                     _ptr(sp.alive), _ptr(part))
+            out += part
+        return out
+
+    def energies(self):
+        """Field energy and the kinetic energy of every species, summed."""
+        wf = C.c_double()
+        wk = C.c_double()
+        total_k = 0.0
+        for k, sp in enumerate(self.species):
+            lib().oracle_energies(C.byref(self._cfg(sp)), sp.np, _ptr(sp.u), _ptr(sp.q),
+                                  _ptr(sp.alive), _ptr(self.E), _ptr(self.B), C.byref(wf),
+                                  C.byref(wk))
+            total_k += wk.value
+        return wf.value, total_k
 
 
 def divergence(cfg: Config, V):

@@ -73,6 +73,15 @@ void oracle_push_deposit(const oracle_config* cfg, int64_t np, double* X,
                          const double* E, const double* B, double* J,
                          int32_t nthreads);
 
+/* Same as oracle_push_deposit for one species (charge-to-mass ratio
+ * cfg->q_over_m) but J is accumulated, not zeroed.  With mobile ions (the
+ * LWFA-1 run of Sec. 6) each species is pushed in the same fields and the
+ * current of the loop of Sec. 2 is the sum of the species' currents. */
+void oracle_push_deposit_add(const oracle_config* cfg, int64_t np, double* X,
+                             double* u, const double* q, int8_t* alive,
+                             const double* E, const double* B, double* J,
+                             int32_t nthreads);
+
 /* FDTD (Yee) advance E^n,B^n -> E^{n+1},B^{n+1} with J^{n+1/2}:
  * B -= dt/2 curl E; E += dt (curl B - J) (Mur-1 on open faces); B -= dt/2 curl E. */
 void oracle_field_advance(const oracle_config* cfg, double* E, double* B,
@@ -101,7 +110,8 @@ void oracle_deposit_rho(const oracle_config* cfg, int64_t np, const double* X,
 void oracle_divergence(const oracle_config* cfg, const double* V, double* out);
 
 /* Field energy 1/2 sum (E^2 + B^2) dV over the samples inside the domain and
- * kinetic energy sum |q| dV (gamma - 1) over live particles. */
+ * kinetic energy sum (q / (q/m)) dV (gamma - 1) over live particles (the
+ * macro-particle's mass density times gamma - 1). */
 void oracle_energies(const oracle_config* cfg, int64_t np, const double* u,
                      const double* q, const int8_t* alive, const double* E,
                      const double* B, double* w_field, double* w_kin);

@@ -372,8 +372,8 @@ void advance_particle(const Grid& g, R* X, R* u, double q, int8_t* alive,
 
 template <class R>
 void push_deposit_impl(const Grid& g, long np, R* X, R* u, const double* q,
-                       int8_t* alive, const R* E, const R* B, R* J) {
-  std::fill(J, J + 3 * g.ncell(), R(0.0));
+                       int8_t* alive, const R* E, const R* B, R* J, bool add = false) {
+  if (!add) std::fill(J, J + 3 * g.ncell(), R(0.0));
   for (long p = 0; p < np; ++p) {
     if (!alive[p]) continue;
     advance_particle(g, X + 3 * p, u + 3 * p, q[p], alive + p, E, B, J);
@@ -385,7 +385,7 @@ void push_deposit_impl(const Grid& g, long np, R* X, R* u, const double* q,
 // copies are reduced into J, the reduction also split over the threads.
 void push_deposit_threads(const Grid& g, long np, double* X, double* u,
                           const double* q, int8_t* alive, const double* E,
-                          const double* B, double* J, int nthreads) {
+                          const double* B, double* J, int nthreads, bool add = false) {
   const long len = 3 * g.ncell();
   std::vector<double> copies((size_t)nthreads * len, 0.0);
 #ifdef _OPENMP
@@ -409,7 +409,7 @@ void push_deposit_threads(const Grid& g, long np, double* X, double* u,
     for (long i = 0; i < len; ++i) {
       double s = 0.0;
       for (int c = 0; c < nthreads; ++c) s += copies[(size_t)c * len + i];
-      J[i] = s;
+      J[i] = add ? J[i] + s : s;
     }
   }
 }
@@ -610,6 +610,17 @@ void oracle_push_deposit(const oracle_config* cfg, int64_t np, double* X,
     push_deposit_impl(g, np, X, u, q, alive, E, B, J);
 }
 
+void oracle_push_deposit_add(const oracle_config* cfg, int64_t np, double* X,
+                             double* u, const double* q, int8_t* alive,
+                             const double* E, const double* B, double* J,
+                             int32_t nthreads) {
+  Grid g(*cfg);
+  if (nthreads > 1)
+    push_deposit_threads(g, np, X, u, q, alive, E, B, J, nthreads, true);
+  else
+    push_deposit_impl(g, np, X, u, q, alive, E, B, J, true);
+}
+
 void oracle_field_advance(const oracle_config* cfg, double* E, double* B,
                           const double* J) {
   Grid g(*cfg);
@@ -726,7 +737,7 @@ void oracle_energies(const oracle_config* cfg, int64_t np, const double* u,
     if (!alive[p]) continue;
     const double* up = u + 3 * p;
     double gam = std::sqrt(1.0 + up[0] * up[0] + up[1] * up[1] + up[2] * up[2]);
-    wk += std::fabs(q[p]) * (gam - 1.0);
+    wk += std::fabs(q[p] / g.qm) * (gam - 1.0);  // macro-particle mass density
   }
   *w_field = 0.5 * wf * dV;
   *w_kin = wk * dV;

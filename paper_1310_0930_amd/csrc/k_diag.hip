@@ -169,10 +169,11 @@ __global__ void __launch_bounds__(256) k_diag_fields(DiagParams P, const R* E0, 
     for (int k = 0; k < NPART; ++k) part[(long)blockIdx.x * NPART + k] = red[k][0];
 }
 
-// Per-block partials: [sum |q|(gamma-1), live count]
+// Per-block partials: [sum m (gamma-1), live count] with the macro-particle
+// mass density m = |q| / |q/m| (minv = 1 / |q/m|)
 template <typename R>
 __global__ void __launch_bounds__(256) k_diag_particles(const int* __restrict__ cell, const R* u0, const R* u1,
-                                 const R* u2, const R* q, double qc, long np,
+                                 const R* u2, const R* q, double qc, double minv, long np,
                                  double* __restrict__ part) {
   __shared__ double red[2][256];
   double wk = 0.0, alive = 0.0;
@@ -180,7 +181,7 @@ __global__ void __launch_bounds__(256) k_diag_particles(const int* __restrict__ 
     if (cell[p] < 0) continue;
     const double ux = u0[p], uy = u1[p], uz = u2[p];
     const double g = sqrt(1.0 + ux * ux + uy * uy + uz * uz);
-    wk += fabs(q ? (double)q[p] : qc) * (g - 1.0);
+    wk += fabs(q ? (double)q[p] : qc) * minv * (g - 1.0);
     alive += 1.0;
   }
   red[0][threadIdx.x] = wk;
@@ -234,10 +235,11 @@ static void rho_t(const DiagParams& P, const pic_particles* p, double qc, double
 }
 
 int launch_deposit_rho(const pic_ctx* ctx, const pic_particles* p, double* rho, void* /*ws*/,
-                       hipStream_t s) {
+                       hipStream_t s, bool accumulate) {
   DiagParams P = diag_params(ctx);
-  k_fill_d<<<dim3((unsigned)((P.ncell + 255) / 256 < 4096 ? (P.ncell + 255) / 256 : 4096)), dim3(256), 0, s>>>(
-      rho, P.ncell);
+  if (!accumulate)
+    k_fill_d<<<dim3((unsigned)((P.ncell + 255) / 256 < 4096 ? (P.ncell + 255) / 256 : 4096)),
+               dim3(256), 0, s>>>(rho, P.ncell);
   const bool dbl = ctx->cfg.real_bytes == 8;
   const int D = P.dims, O = P.order;
   const double qc = ctx->cfg.q_const;
@@ -253,51 +255,69 @@ int launch_deposit_rho(const pic_ctx* ctx, const pic_particles* p, double* rho, 
   return (int)hipGetLastError();
 }
 
+// Diagnostics of one or more species sharing the fields: rho is the sum of
+// the species' charge densities; the kinetic energy sums every species'
+// mass density (q over q/m) times gamma - 1.  Each species' particle
+// partials go to the diagnostics scratch of its own workspace.
 template <typename R>
-static int diag_t(const pic_ctx* ctx, const pic_particles* p, const pic_fields* f,
-                  const double* rho_prev, const double* gauss_ref, double* rho_out,
-                  double* gauss_out, pic_diag* out, void* ws, hipStream_t s) {
-  DiagParams P = diag_params(ctx);
-  int err = launch_deposit_rho(ctx, p, rho_out, ws, s);
-  if (err) return err;
-  WsLayout L = ws_layout(ctx, p->np);
-  double* part = (double*)((char*)ws + L.diag);
+static int diag_t(int ns, const pic_ctx* const* ctx, const pic_particles* const* p,
+                  void* const* ws, const pic_fields* f, const double* rho_prev,
+                  const double* gauss_ref, double* rho_out, double* gauss_out, pic_diag* out,
+                  hipStream_t s) {
+  DiagParams P = diag_params(ctx[0]);
+  for (int k = 0; k < ns; ++k) {
+    int err = launch_deposit_rho(ctx[k], p[k], rho_out, ws[k], s, k > 0);
+    if (err) return err;
+  }
+  WsLayout L0 = ws_layout(ctx[0], p[0]->np);
+  double* part = (double*)((char*)ws[0] + L0.diag);
   const unsigned gf = (unsigned)((P.ncell + 255) / 256);
   k_diag_fields<R><<<dim3(gf), dim3(256), 0, s>>>(
       P, (const R*)f->E[0], (const R*)f->E[1], (const R*)f->E[2], (const R*)f->B[0],
       (const R*)f->B[1], (const R*)f->B[2], (const R*)f->J[0], (const R*)f->J[1],
       (const R*)f->J[2], rho_out, rho_prev, gauss_ref, gauss_out, part);
   const unsigned gp = 1024;
-  double* ppart = part + (size_t)gf * NPART;
-  k_diag_particles<R><<<dim3(gp), dim3(256), 0, s>>>(p->cell, (const R*)p->u[0], (const R*)p->u[1],
-                                                    (const R*)p->u[2], (const R*)p->q,
-                                                    ctx->cfg.q_const, p->np, ppart);
-  err = (int)hipGetLastError();
+  for (int k = 0; k < ns; ++k) {
+    WsLayout Lk = ws_layout(ctx[k], p[k]->np);
+    double* ppart = (double*)((char*)ws[k] + Lk.diag) + (size_t)gf * NPART;
+    const double minv = 1.0 / fabs(ctx[k]->cfg.q_over_m);
+    k_diag_particles<R><<<dim3(gp), dim3(256), 0, s>>>(
+        p[k]->cell, (const R*)p[k]->u[0], (const R*)p[k]->u[1], (const R*)p[k]->u[2],
+        (const R*)p[k]->q, ctx[k]->cfg.q_const, minv, p[k]->np, ppart);
+  }
+  int err = (int)hipGetLastError();
   if (err) return err;
   const size_t nfp = (size_t)gf * NPART + 2 * gp;
   double* host = (double*)malloc(nfp * sizeof(double));
   if (!host) return (int)hipErrorOutOfMemory;
-  err = (int)hipMemcpyAsync(host, part, nfp * sizeof(double), hipMemcpyDeviceToHost, s);
-  if (!err) err = (int)hipStreamSynchronize(s);
-  if (err) {
-    free(host);
-    return err;
-  }
   double gmax = 0, rmax = 0, c2 = 0, cmax = 0, d2 = 0, wf = 0, wk = 0, alive = 0;
-  for (unsigned b = 0; b < gf; ++b) {
-    const double* v = host + (size_t)b * NPART;
-    gmax = fmax(gmax, v[0]);
-    rmax = fmax(rmax, v[1]);
-    c2 += v[2];
-    cmax = fmax(cmax, v[3]);
-    d2 += v[4];
-    wf += v[5];
-  }
-  for (unsigned b = 0; b < gp; ++b) {
-    wk += host[(size_t)gf * NPART + 2 * b];
-    alive += host[(size_t)gf * NPART + 2 * b + 1];
+  for (int k = 0; k < ns && !err; ++k) {
+    WsLayout Lk = ws_layout(ctx[k], p[k]->np);
+    const double* src = (const double*)((const char*)ws[k] + Lk.diag);
+    // species 0 brings the field partials as well
+    const size_t off = k == 0 ? 0 : (size_t)gf * NPART;
+    err = (int)hipMemcpyAsync(host + off, src + off, (nfp - off) * sizeof(double),
+                              hipMemcpyDeviceToHost, s);
+    if (!err) err = (int)hipStreamSynchronize(s);
+    if (err) break;
+    if (k == 0) {
+      for (unsigned b = 0; b < gf; ++b) {
+        const double* v = host + (size_t)b * NPART;
+        gmax = fmax(gmax, v[0]);
+        rmax = fmax(rmax, v[1]);
+        c2 += v[2];
+        cmax = fmax(cmax, v[3]);
+        d2 += v[4];
+        wf += v[5];
+      }
+    }
+    for (unsigned b = 0; b < gp; ++b) {
+      wk += host[(size_t)gf * NPART + 2 * b];
+      alive += host[(size_t)gf * NPART + 2 * b + 1];
+    }
   }
   free(host);
+  if (err) return err;
   out->gauss_max = gmax;
   out->rho_max = rmax;
   out->gauss_rel = rmax > 0 ? gmax / rmax : 0.0;
@@ -310,12 +330,13 @@ static int diag_t(const pic_ctx* ctx, const pic_particles* p, const pic_fields* 
   return 0;
 }
 
-int launch_diagnostics(const pic_ctx* ctx, const pic_particles* p, const pic_fields* f,
-                       const double* rho_prev, const double* gauss_ref, double* rho_out,
-                       double* gauss_out, pic_diag* out, void* ws, hipStream_t s) {
-  return ctx->cfg.real_bytes == 8
-             ? diag_t<double>(ctx, p, f, rho_prev, gauss_ref, rho_out, gauss_out, out, ws, s)
-             : diag_t<float>(ctx, p, f, rho_prev, gauss_ref, rho_out, gauss_out, out, ws, s);
+int launch_diagnostics(int ns, const pic_ctx* const* ctx, const pic_particles* const* p,
+                       void* const* ws, const pic_fields* f, const double* rho_prev,
+                       const double* gauss_ref, double* rho_out, double* gauss_out, pic_diag* out,
+                       hipStream_t s) {
+  return ctx[0]->cfg.real_bytes == 8
+             ? diag_t<double>(ns, ctx, p, ws, f, rho_prev, gauss_ref, rho_out, gauss_out, out, s)
+             : diag_t<float>(ns, ctx, p, ws, f, rho_prev, gauss_ref, rho_out, gauss_out, out, s);
 }
 
 long diag_len(const pic_config& cf) {

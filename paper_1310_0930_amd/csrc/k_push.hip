@@ -319,7 +319,8 @@ __global__ void __launch_bounds__(256) k_push_deferred(KParams<R> P, DParts<R> p
   if (blockIdx.x == 0 && threadIdx.x == 0 && nd > 0) atomicAdd(&flg->slowpath, (unsigned long long)nd);
 }
 
-// Zero J and the deferred-list length before a push.
+// Zero J (n = 0: keep it, another species adds its current) and the
+// deferred-list length before a push.
 template <typename R>
 __global__ void k_push_prologue(R* a, R* b, R* c, long n, DevFlags* flg) {
   if (blockIdx.x == 0 && threadIdx.x == 0) flg->ndefer = 0u;
@@ -332,7 +333,7 @@ __global__ void k_push_prologue(R* a, R* b, R* c, long n, DevFlags* flg) {
 
 template <int DIMS, int ORDER, typename R>
 static int launch_pd(const pic_ctx* ctx, const pic_particles* p, const pic_fields* f, void* ws,
-                     hipStream_t s) {
+                     hipStream_t s, bool accumulate) {
   using G = Geo<DIMS, ORDER, R>;
   KParams<R> P = make_params<R>(ctx);
   WsLayout L = ws_layout(ctx, p->np);
@@ -353,9 +354,9 @@ static int launch_pd(const pic_ctx* ctx, const pic_particles* p, const pic_field
   }
   DevFlags* flg = (DevFlags*)(w + L.flags);
   int* deferred = (int*)(w + L.tmp_cell);  // the sort's scratch is free during a push
-  const long ncell = (long)P.n[0] * P.n[1] * P.n[2];
+  const long ncell = accumulate ? 0L : (long)P.n[0] * P.n[1] * P.n[2];
   const long fb = (ncell + 255) / 256;
-  k_push_prologue<R><<<dim3((unsigned)(fb < 4096 ? fb : 4096)), dim3(256), 0, s>>>(
+  k_push_prologue<R><<<dim3((unsigned)(fb < 1 ? 1 : fb < 4096 ? fb : 4096)), dim3(256), 0, s>>>(
       F.J[0], F.J[1], F.J[2], ncell, flg);
   k_push_tile<DIMS, ORDER, R><<<dim3(8 * P.per_xcd), dim3(G::NT), 0, s>>>(
       P, pa, F, (const int*)(w + L.starts), deferred, flg);
@@ -364,13 +365,13 @@ static int launch_pd(const pic_ctx* ctx, const pic_particles* p, const pic_field
 }
 
 int launch_push_deposit(const pic_ctx* ctx, const pic_particles* p, const pic_fields* f, void* ws,
-                        hipStream_t s) {
+                        hipStream_t s, bool accumulate) {
   const int D = ctx->cfg.dims, O = ctx->cfg.order;
   const bool dbl = ctx->cfg.real_bytes == 8;
 #define PIC_PD(DD, OO)                                                            \
   if (D == DD && O == OO)                                                         \
-    return dbl ? launch_pd<DD, OO, double>(ctx, p, f, ws, s)                     \
-               : launch_pd<DD, OO, float>(ctx, p, f, ws, s);
+    return dbl ? launch_pd<DD, OO, double>(ctx, p, f, ws, s, accumulate)         \
+               : launch_pd<DD, OO, float>(ctx, p, f, ws, s, accumulate);
   PIC_PD(2, 1) PIC_PD(2, 2) PIC_PD(2, 3) PIC_PD(3, 1) PIC_PD(3, 2) PIC_PD(3, 3)
 #undef PIC_PD
   return (int)hipErrorInvalidValue;

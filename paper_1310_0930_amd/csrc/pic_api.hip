@@ -251,7 +251,19 @@ int pic_push_deposit(pic_ctx* ctx, pic_particles* p, const pic_fields* f, void* 
   if (ctx->sorted_cell != p->cell || ctx->sorted_ws != ws || ctx->sorted_np != p->np)
     return PIC_ESTATE;
   if ((v = ensure_device(ctx))) return v;
-  return hip_status(launch_push_deposit(ctx, p, f, ws, (hipStream_t)stream));
+  return hip_status(launch_push_deposit(ctx, p, f, ws, (hipStream_t)stream, false));
+}
+
+int pic_push_deposit_add(pic_ctx* ctx, pic_particles* p, const pic_fields* f, void* ws,
+                         void* stream) {
+  if (!ctx || !ws) return PIC_EINVAL;
+  int v = check_particles(ctx, p);
+  if (v) return v;
+  if ((v = check_fields(f, true))) return v;
+  if (ctx->sorted_cell != p->cell || ctx->sorted_ws != ws || ctx->sorted_np != p->np)
+    return PIC_ESTATE;
+  if ((v = ensure_device(ctx))) return v;
+  return hip_status(launch_push_deposit(ctx, p, f, ws, (hipStream_t)stream, true));
 }
 
 int pic_field_advance(pic_ctx* ctx, pic_fields* f, void* ws, void* stream) {
@@ -275,6 +287,55 @@ int pic_step(pic_ctx* ctx, pic_particles* p, pic_fields* f, int32_t nsteps, void
     if ((v = pic_push_deposit(ctx, p, f, ws, stream))) return v;
     if ((v = pic_field_advance(ctx, f, ws, stream))) return v;
     ctx->steps_done += 1;
+  }
+  return PIC_OK;
+}
+
+// Species that share fields must share the grid, the time step, the shape
+// order, the precision and the boundaries.
+static bool same_grid(const pic_ctx* a, const pic_ctx* b) {
+  const pic_config &x = a->cfg, &y = b->cfg;
+  if (x.dims != y.dims || x.order != y.order || x.real_bytes != y.real_bytes || x.dt != y.dt)
+    return false;
+  for (int d = 0; d < x.dims; ++d)
+    if (x.n[d] != y.n[d] || x.dx[d] != y.dx[d] || x.bc[d] != y.bc[d]) return false;
+  return a->device == b->device;
+}
+
+static int check_species(int32_t ns, pic_ctx* const* ctx, const pic_particles* const* p,
+                         void* const* ws) {
+  if (ns < 1 || !ctx || !p || !ws) return PIC_EINVAL;
+  for (int32_t k = 0; k < ns; ++k) {
+    if (!ctx[k] || !ws[k]) return PIC_EINVAL;
+    int v = check_particles(ctx[k], p[k]);
+    if (v) return v;
+    if (!same_grid(ctx[0], ctx[k])) return PIC_EINVAL;
+    for (int32_t j = 0; j < k; ++j)
+      if (ctx[j] == ctx[k] || ws[j] == ws[k]) return PIC_EINVAL;
+  }
+  return PIC_OK;
+}
+
+int pic_step_species(int32_t nspecies, pic_ctx* const* ctx, pic_particles* const* p,
+                     void* const* ws, pic_fields* f, int32_t nsteps, void* stream) {
+  if (nsteps < 0) return PIC_EINVAL;
+  int v = check_species(nspecies, ctx, p, ws);
+  if (v) return v;
+  if ((v = check_fields(f, true))) return v;
+  for (int32_t s = 0; s < nsteps; ++s) {
+    for (int32_t k = 0; k < nspecies; ++k) {
+      pic_ctx* c = ctx[k];
+      const bool sorted = c->sorted_cell == p[k]->cell && c->sorted_ws == ws[k] &&
+                          c->sorted_np == p[k]->np;
+      if (!sorted || c->steps_done % c->cfg.sort_every == 0) {
+        if ((v = pic_sort(c, p[k], ws[k], stream))) return v;
+      }
+      v = k == 0 ? pic_push_deposit(c, p[k], f, ws[k], stream)
+                 : pic_push_deposit_add(c, p[k], f, ws[k], stream);
+      if (v) return v;
+    }
+    if ((v = pic_field_advance(ctx[0], f, ws[0], stream))) return v;
+    for (int32_t k = 0; k < nspecies; ++k) ctx[k]->steps_done += 1;
   }
   return PIC_OK;
 }
@@ -310,27 +371,47 @@ int pic_deposit_rho(pic_ctx* ctx, const pic_particles* p, double* rho, void* ws,
   int v = check_particles(ctx, p);
   if (v) return v;
   if ((v = ensure_device(ctx))) return v;
-  return hip_status(launch_deposit_rho(ctx, p, rho, ws, (hipStream_t)stream));
+  return hip_status(launch_deposit_rho(ctx, p, rho, ws, (hipStream_t)stream, false));
+}
+
+int pic_deposit_rho_add(pic_ctx* ctx, const pic_particles* p, double* rho, void* ws, void* stream) {
+  if (!ctx || !rho) return PIC_EINVAL;
+  int v = check_particles(ctx, p);
+  if (v) return v;
+  if ((v = ensure_device(ctx))) return v;
+  return hip_status(launch_deposit_rho(ctx, p, rho, ws, (hipStream_t)stream, true));
+}
+
+int pic_diagnostics_species(int32_t nspecies, pic_ctx* const* ctx, const pic_particles* const* p,
+                            void* const* ws, const pic_fields* f, const double* rho_prev,
+                            const double* gauss_ref, double* rho_out, double* gauss_out,
+                            pic_diag* out, void* stream) {
+  if (!rho_out || !out) return PIC_EINVAL;
+  int v = check_species(nspecies, ctx, p, ws);
+  if (v) return v;
+  if ((v = check_fields(f, true))) return v;
+  if ((v = ensure_device(ctx[0]))) return v;
+  memset(out, 0, sizeof(*out));
+  v = hip_status(launch_diagnostics(nspecies, ctx, p, ws, f, rho_prev, gauss_ref, rho_out,
+                                    gauss_out, out, (hipStream_t)stream));
+  if (v) return v;
+  for (int32_t k = 0; k < nspecies; ++k) {
+    uint32_t flags = 0;
+    int64_t slow = 0;
+    v = pic_read_flags(ctx[k], ws[k], 0, &flags, &slow, stream);
+    if (v != PIC_OK && v != PIC_EDEVICE) return v;
+    out->flags |= flags;
+    out->n_slowpath += slow;
+  }
+  return PIC_OK;
 }
 
 int pic_diagnostics(pic_ctx* ctx, const pic_particles* p, const pic_fields* f,
                     const double* rho_prev, const double* gauss_ref, double* rho_out,
                     double* gauss_out, pic_diag* out, void* ws, void* stream) {
-  if (!ctx || !ws || !rho_out || !out) return PIC_EINVAL;
-  int v = check_particles(ctx, p);
-  if (v) return v;
-  if ((v = check_fields(f, true))) return v;
-  if ((v = ensure_device(ctx))) return v;
-  memset(out, 0, sizeof(*out));
-  v = hip_status(launch_diagnostics(ctx, p, f, rho_prev, gauss_ref, rho_out, gauss_out, out, ws,
-                                    (hipStream_t)stream));
-  if (v) return v;
-  uint32_t flags = 0;
-  int64_t slow = 0;
-  v = pic_read_flags(ctx, ws, 0, &flags, &slow, stream);
-  out->flags = flags;
-  out->n_slowpath = slow;
-  return v == PIC_EDEVICE ? PIC_OK : v;
+  if (!ctx || !ws || !p) return PIC_EINVAL;
+  return pic_diagnostics_species(1, &ctx, &p, &ws, f, rho_prev, gauss_ref, rho_out, gauss_out,
+                                 out, stream);
 }
 
 int pic_read_flags(pic_ctx* ctx, void* ws, int clear, uint32_t* flags, int64_t* n_slowpath,

@@ -175,17 +175,18 @@ WsLayout ws_layout(const pic_ctx* ctx, int64_t np);
 // launchers (return hipError_t as int)
 int launch_sort(const pic_ctx* ctx, const pic_particles* p, void* ws, hipStream_t s);
 int launch_push_deposit(const pic_ctx* ctx, const pic_particles* p, const pic_fields* f,
-                        void* ws, hipStream_t s);
+                        void* ws, hipStream_t s, bool accumulate);
 int launch_field_advance(const pic_ctx* ctx, const pic_fields* f, void* ws, hipStream_t s);
 int launch_field_advance_adjoint(const pic_ctx* ctx, const pic_fields* lam, void* ws, hipStream_t s);
 int launch_push_deposit_adjoint(const pic_ctx* ctx, const pic_particles* p, const pic_fields* f,
                                 const pic_fields* lam_f, pic_particles* lam_p, void* ws,
                                 hipStream_t s);
 int launch_deposit_rho(const pic_ctx* ctx, const pic_particles* p, double* rho, void* ws,
+                       hipStream_t s, bool accumulate);
+int launch_diagnostics(int ns, const pic_ctx* const* ctx, const pic_particles* const* p,
+                       void* const* ws, const pic_fields* f, const double* rho_prev,
+                       const double* gauss_ref, double* rho_out, double* gauss_out, pic_diag* out,
                        hipStream_t s);
-int launch_diagnostics(const pic_ctx* ctx, const pic_particles* p, const pic_fields* f,
-                       const double* rho_prev, const double* gauss_ref, double* rho_out,
-                       double* gauss_out, pic_diag* out, void* ws, hipStream_t s);
 
 template <typename R>
 KParams<R> make_params(const pic_ctx* ctx);

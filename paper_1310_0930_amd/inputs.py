@@ -15,6 +15,8 @@ plasma with a Gaussian pulse placed in the box):
 * momenta: u_i ~ N(0, u_th^2) per component, rounded to FP32;
 * charge: q_p = -n(x_p)/ppc with n = 1 (uniform) or n = min(x/L_ramp, 1)
   (linear ramp along x), rounded to FP32;
+* ions (optional, ``Workload.ions``): drawn the same way from child seeds
+  of their own, charge +n(x)/ppc, charge-to-mass ratio Z/M;
 * laser: E_y = a0 w0/wp exp(-r^2/W^2) exp(-(x-xc)^2/tau^2) cos(k0 (x-xc)),
   cut to zero for |x - xc| > 3 tau, B_z = the same profile at B_z's position
   (a forward-moving pulse), rounded to FP32.
@@ -48,6 +50,21 @@ class Laser:
 
 
 @dataclass(frozen=True)
+class Ions:
+    """A mobile ion species (the paper's LWFA-1 run keeps the ions mobile,
+    Sec. 6): charge state Z, mass ratio M = m_i/m_e, thermal spread u_th.
+    Drawn like the electrons (ppc per cell, own seeds), charge +n(x)/ppc per
+    macro-ion (neutralising), charge-to-mass ratio Z/M in units of e/m_e."""
+    mass_ratio: float = 1836.15
+    charge: float = 1.0
+    u_th: float = 0.0
+
+    @property
+    def q_over_m(self) -> float:
+        return self.charge / self.mass_ratio
+
+
+@dataclass(frozen=True)
 class Workload:
     name: str
     dims: int
@@ -63,6 +80,7 @@ class Workload:
     laser: Laser | None = None
     sort_every: int = 20
     seed: int = SEED_BASE
+    ions: Ions | None = None
 
     @property
     def dt(self) -> float:
@@ -99,6 +117,11 @@ class Workload:
     def q_const(self) -> float:
         """Charge of one macro-electron at density n0 = 1, rounded to FP32."""
         return float(np.float32(-1.0 / self.ppc))
+
+    @property
+    def q_const_ions(self) -> float:
+        """Charge of one macro-ion at n0 = 1 (neutralising), rounded to FP32."""
+        return float(np.float32(1.0 / self.ppc))
 
     def with_(self, **kw) -> "Workload":
         return replace(self, **kw)
@@ -184,6 +207,19 @@ def make_plasma(w: Workload, slabs: range | None = None, quiet: bool = False) ->
     those slabs.  ``quiet`` places the particles on a regular sub-lattice
     (for cold-plasma tests) instead of drawing the offsets.
     """
+    return _draw(w, slabs, quiet, stream=(), u_th=w.u_th, sign=-1.0, q_const=w.q_const)
+
+
+def make_ions(w: Workload, slabs: range | None = None, quiet: bool = False) -> Plasma:
+    """Draw the ion species of workload ``w`` (``w.ions``): the same cells and
+    ppc as the electrons, offsets and momenta from child seeds of their own,
+    charge +n(x)/ppc."""
+    if w.ions is None:
+        raise ValueError(f"workload {w.name} has no ion species")
+    return _draw(w, slabs, quiet, stream=(1,), u_th=w.ions.u_th, sign=1.0, q_const=w.q_const_ions)
+
+
+def _draw(w, slabs, quiet, stream, u_th, sign, q_const) -> Plasma:
     pc = w.particle_cells()
     n0, n1, _ = w.n3
     if w.dims == 3:
@@ -202,7 +238,7 @@ def make_plasma(w: Workload, slabs: range | None = None, quiet: bool = False) ->
     else:
         base_cells = np.arange(pc[0], dtype=np.int64)
     for t, s in enumerate(slabs):
-        rng = np.random.default_rng([w.seed, int(s)])
+        rng = np.random.default_rng([w.seed, int(s), *stream])
         lo, hi = t * per_slab, (t + 1) * per_slab
         slab_cells = base_cells + (n0 * n1 * s if w.dims == 3 else n0 * s)
         cell[lo:hi] = np.repeat(slab_cells, w.ppc).astype(np.int32)
@@ -216,14 +252,14 @@ def make_plasma(w: Workload, slabs: range | None = None, quiet: bool = False) ->
                 off[d, lo:hi] = np.tile(sub[d], cells_per_slab).astype(np.float32)
         else:
             off[:, lo:hi] = _uniform_offsets(rng, per_slab, w.dims)
-        if w.u_th > 0.0:
-            u[:, lo:hi] = _round32(rng.normal(0.0, w.u_th, size=(3, per_slab)))
+        if u_th > 0.0:
+            u[:, lo:hi] = _round32(rng.normal(0.0, u_th, size=(3, per_slab)))
     q = None
     if w.ramp_cells > 0.0:
-        X = Plasma(cell, off, u, None, w.q_const).global_positions(w)[:, 0]
+        X = Plasma(cell, off, u, None, q_const).global_positions(w)[:, 0]
         dens = np.clip(X / w.ramp_cells, 0.0, 1.0)
-        q = _round32(-dens / w.ppc)
-    return Plasma(cell, off, u, q, w.q_const)
+        q = _round32(sign * dens / w.ppc)
+    return Plasma(cell, off, u, q, q_const)
 
 
 def laser_fields(w: Workload, a0: float | None = None) -> tuple[np.ndarray, np.ndarray]:

@@ -1,14 +1,17 @@
 """Thin ctypes binding of libpic (``include/pic.h``).
 
 The module-level functions carry the C names (``pic_create``, ``pic_sort``,
-``pic_push_deposit``, ``pic_field_advance``, ``pic_step``,
-``pic_deposit_rho``, ``pic_diagnostics``, ``pic_read_flags``) and only
+``pic_push_deposit``, ``pic_push_deposit_add``, ``pic_field_advance``,
+``pic_step``, ``pic_step_species``, ``pic_deposit_rho``,
+``pic_deposit_rho_add``, ``pic_diagnostics``, ``pic_diagnostics_species``,
+``pic_read_flags``, the adjoints) and only
 marshal arguments: every step of the method runs in the HIP kernels of
 ``libpic.so``.  PyTorch provides device memory and the stream.  There is no
 fallback: a missing library raises.
 
 ``Simulation`` bundles one context with its particle, field and workspace
-tensors (SoA, FP32 or FP64).
+tensors (SoA, FP32 or FP64); ``add_species`` attaches further species
+(mobile ions) that share its fields.
 """
 from __future__ import annotations
 
@@ -75,6 +78,15 @@ _SIGS = {
     "pic_diagnostics": ([C.c_void_p, C.POINTER(PicParticles), C.POINTER(PicFields), C.c_void_p,
                          C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(PicDiag), C.c_void_p,
                          C.c_void_p], C.c_int),
+    "pic_push_deposit_add": ([C.c_void_p, C.POINTER(PicParticles), C.POINTER(PicFields),
+                              C.c_void_p, C.c_void_p], C.c_int),
+    "pic_step_species": ([C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(PicFields),
+                          C.c_int32, C.c_void_p], C.c_int),
+    "pic_deposit_rho_add": ([C.c_void_p, C.POINTER(PicParticles), C.c_void_p, C.c_void_p,
+                             C.c_void_p], C.c_int),
+    "pic_diagnostics_species": ([C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                 C.POINTER(PicFields), C.c_void_p, C.c_void_p, C.c_void_p,
+                                 C.c_void_p, C.POINTER(PicDiag), C.c_void_p], C.c_int),
     "pic_field_advance_adjoint": ([C.c_void_p, C.POINTER(PicFields), C.c_void_p, C.c_void_p],
                                   C.c_int),
     "pic_push_deposit_adjoint": ([C.c_void_p, C.POINTER(PicParticles), C.POINTER(PicFields),
@@ -178,6 +190,41 @@ def pic_diagnostics(ctx, parts, fields, rho_prev, gauss_ref, rho_out, gauss_out,
     return d
 
 
+def _species_arrays(ctxs, parts, wss):
+    n = len(ctxs)
+    if not (len(parts) == n and len(wss) == n):
+        raise ValueError("one context, particle set and workspace per species")
+    pa = (C.POINTER(PicParticles) * n)(*[C.pointer(p) for p in parts])
+    return (C.c_void_p * n)(*[C.cast(c, C.c_void_p) for c in ctxs]), pa, (C.c_void_p * n)(*wss)
+
+
+def pic_push_deposit_add(ctx, parts: PicParticles, fields: PicFields, ws, stream=None):
+    _check(lib().pic_push_deposit_add(ctx, C.byref(parts), C.byref(fields), C.c_void_p(ws),
+                                      _stream(stream)), "pic_push_deposit_add")
+
+
+def pic_step_species(ctxs, parts, wss, fields: PicFields, nsteps, stream=None):
+    c, p, w = _species_arrays(ctxs, parts, wss)
+    _check(lib().pic_step_species(len(ctxs), c, p, w, C.byref(fields), int(nsteps), _stream(stream)),
+           "pic_step_species")
+
+
+def pic_deposit_rho_add(ctx, parts: PicParticles, rho_ptr, ws, stream=None):
+    _check(lib().pic_deposit_rho_add(ctx, C.byref(parts), C.c_void_p(rho_ptr), C.c_void_p(ws),
+                                     _stream(stream)), "pic_deposit_rho_add")
+
+
+def pic_diagnostics_species(ctxs, parts, wss, fields, rho_prev, gauss_ref, rho_out, gauss_out,
+                            stream=None):
+    c, p, w = _species_arrays(ctxs, parts, wss)
+    d = PicDiag()
+    _check(lib().pic_diagnostics_species(len(ctxs), c, p, w, C.byref(fields),
+                                         C.c_void_p(rho_prev or 0), C.c_void_p(gauss_ref or 0),
+                                         C.c_void_p(rho_out), C.c_void_p(gauss_out or 0),
+                                         C.byref(d), _stream(stream)), "pic_diagnostics_species")
+    return d
+
+
 def pic_field_advance_adjoint(ctx, lam_fields: PicFields, ws, stream=None):
     _check(lib().pic_field_advance_adjoint(ctx, C.byref(lam_fields), C.c_void_p(ws), _stream(stream)),
            "pic_field_advance_adjoint")
@@ -247,6 +294,22 @@ class Simulation:
                                  (C.c_void_p * 3)(*[self.B[c].data_ptr() for c in range(3)]),
                                  (C.c_void_p * 3)(*[self.J[c].data_ptr() for c in range(3)]))
 
+        self.species = []  # further species sharing these fields (add_species)
+        self.q_over_m = q_over_m
+
+    def add_species(self, plasma, q_over_m, q_const, with_id=True):
+        """Another species on this grid (mobile ions): its own context (q/m,
+        uniform charge), particle arrays and workspace, pushed in and
+        depositing into this simulation's E, B, J.  Returns its Simulation."""
+        c = self.cfg
+        sp = Simulation(self.dims, self.n, tuple(c.dx), c.dt, c.order, c.real_bytes, tuple(c.bc),
+                        c.sort_every, q_over_m, q_const, self.device)
+        sp.E, sp.B, sp.J = self.E, self.B, self.J
+        sp._fields = self._fields
+        sp._load_particles(plasma, with_id)
+        self.species.append(sp)
+        return sp
+
     @classmethod
     def from_workload(cls, w, real_bytes=4, device="cuda", **kw):
         return cls(w.dims, w.n3, w.dx3, w.dt, w.order, real_bytes, w.bc3, w.sort_every, -1.0,
@@ -264,18 +327,23 @@ class Simulation:
     def load(self, plasma, E=None, B=None, with_id=True):
         """Upload a Plasma (inputs.Plasma) and initial fields (3, n2, n1, n0)."""
         torch = self.torch
-        self.np = plasma.np
         dev = self.device
-        self.cell = torch.from_numpy(np.ascontiguousarray(plasma.cell)).to(dev)
-        self.off = torch.from_numpy(np.ascontiguousarray(plasma.off)).to(dev, self.real).contiguous()
-        self.u = torch.from_numpy(np.ascontiguousarray(plasma.u)).to(dev, self.real).contiguous()
-        self.q = None if plasma.q is None else torch.from_numpy(plasma.q).to(dev, self.real)
-        self.id = torch.arange(self.np, dtype=torch.int32, device=dev) if with_id else None
         if E is not None:
             self.E.copy_(torch.from_numpy(np.asarray(E).reshape(3, -1)).to(dev, self.real))
         if B is not None:
             self.B.copy_(torch.from_numpy(np.asarray(B).reshape(3, -1)).to(dev, self.real))
         self.J.zero_()
+        return self._load_particles(plasma, with_id)
+
+    def _load_particles(self, plasma, with_id):
+        torch = self.torch
+        dev = self.device
+        self.np = plasma.np
+        self.cell = torch.from_numpy(np.ascontiguousarray(plasma.cell)).to(dev)
+        self.off = torch.from_numpy(np.ascontiguousarray(plasma.off)).to(dev, self.real).contiguous()
+        self.u = torch.from_numpy(np.ascontiguousarray(plasma.u)).to(dev, self.real).contiguous()
+        self.q = None if plasma.q is None else torch.from_numpy(plasma.q).to(dev, self.real)
+        self.id = torch.arange(self.np, dtype=torch.int32, device=dev) if with_id else None
         nbytes = pic_workspace_bytes(self.ctx, self.np)
         self.ws = torch.zeros(nbytes, dtype=torch.uint8, device=dev)
         self._parts = PicParticles(
@@ -329,22 +397,32 @@ class Simulation:
         pic_field_advance(self.ctx, self._fields, self.ws.data_ptr(), self.stream)
 
     def step(self, nsteps=1):
-        pic_step(self.ctx, self._parts, self._fields, nsteps, self.ws.data_ptr(), self.stream)
+        if self.species:
+            all_ = [self] + self.species
+            pic_step_species([s.ctx for s in all_], [s._parts for s in all_],
+                             [s.ws.data_ptr() for s in all_], self._fields, nsteps, self.stream)
+        else:
+            pic_step(self.ctx, self._parts, self._fields, nsteps, self.ws.data_ptr(), self.stream)
 
     def rho(self):
+        """Charge density of all species (FP64, ncell)."""
         r = self.torch.zeros(self.ncell, dtype=self.torch.float64, device=self.device)
         pic_deposit_rho(self.ctx, self._parts, r.data_ptr(), self.ws.data_ptr(), self.stream)
+        for sp in self.species:
+            pic_deposit_rho_add(sp.ctx, sp._parts, r.data_ptr(), sp.ws.data_ptr(), self.stream)
         return r
 
     def diagnostics(self, rho_prev=None, gauss_ref=None, want_gauss=False):
         torch = self.torch
         rho = torch.zeros(self.ncell, dtype=torch.float64, device=self.device)
         g = torch.zeros_like(rho) if want_gauss else None
-        d = pic_diagnostics(self.ctx, self._parts, self._fields,
-                            None if rho_prev is None else rho_prev.data_ptr(),
-                            None if gauss_ref is None else gauss_ref.data_ptr(),
-                            rho.data_ptr(), None if g is None else g.data_ptr(),
-                            self.ws.data_ptr(), self.stream)
+        all_ = [self] + self.species
+        d = pic_diagnostics_species([s.ctx for s in all_], [s._parts for s in all_],
+                                    [s.ws.data_ptr() for s in all_], self._fields,
+                                    None if rho_prev is None else rho_prev.data_ptr(),
+                                    None if gauss_ref is None else gauss_ref.data_ptr(),
+                                    rho.data_ptr(), None if g is None else g.data_ptr(),
+                                    self.stream)
         out = d.as_dict()
         out["gauss_field"] = g
         return Diag(out, rho)

@@ -523,3 +523,112 @@ def test_jvp_matches_central_differences():
     fd_u = (p.u - m.u) / (2 * h)
     assert np.abs(dEo - fd_E).max() < 1e-6 * np.abs(fd_E).max()
     assert np.abs(duo - fd_u).max() < 1e-6 * np.abs(fd_u).max()
+
+
+# ---------------------------------------------------------------- mobile ions
+def _two_species(w, M, quiet=True):
+    """Electrons and ions (q/m = +1/M) of workload w in its fields."""
+    wi = w.with_(ions=I.Ions(mass_ratio=M))
+    pe, pi = I.make_plasma(w, quiet=quiet), I.make_ions(wi, quiet=quiet)
+    E, B = I.laser_fields(w)
+    c = O.Config(w.dims, w.n3, w.dx3, w.dt, w.order, w.bc3)
+    e = O.Species(-1.0, pe.global_positions(w), pe.u.T.astype(np.float64), pe.charges())
+    i = O.Species(1.0 / M, pi.global_positions(wi), pi.u.T.astype(np.float64), pi.charges())
+    return c, O.MultiState(c, [e, i], E, B)
+
+
+def test_two_species_cold_plasma_frequency():
+    """Cold electrons and ions of mass ratio M = 4 on the same quiet lattice
+    (rho = 0), electrons kicked with u_x = d sin(k x): the longitudinal mode
+    of cold two-fluid theory oscillates at omega^2 = omega_pe^2 + omega_pi^2
+    = 1 + 1/M (within 0.5 %), and the ions move against the electrons with
+    1/M of their momentum change per unit charge."""
+    M = 4.0
+    w = I.WORKLOADS["w2d_64_linear"].with_(u_th=0.0)
+    c, s = _two_species(w, M)
+    e, i = s.species
+    k = 2 * np.pi / (w.n[0] * w.dx[0])
+    d = 1e-3
+    e.u[:, 0] = d * np.sin(k * e.X[:, 0] * w.dx[0])
+    x_e = (np.arange(w.n[0]) + 0.5) * w.dx[0]
+    basis = np.sin(k * x_e)
+    ts, amps = [], []
+    for n in range(w.steps):
+        s.step(1)
+        ts.append((n + 1) * c.dt)
+        amps.append(2 * np.mean(s.E[0, 0] * basis[None, :]))
+    from scipy.optimize import curve_fit
+    f = lambda t, A, om, ph: A * np.sin(om * t + ph)  # noqa: E731
+    (A, om, ph), _ = curve_fit(f, np.array(ts), np.array(amps), p0=(d, 1.1, 0.0))
+    assert abs(om / np.sqrt(1.0 + 1.0 / M) - 1.0) < 5e-3
+    # the ion response: du_i/dt = E/M, du_e/dt = -E, so d(u_e + M u_i)/dt = 0
+    xs = e.X[:, 0] * w.dx[0]
+    pe_ = 2 * np.mean(e.u[:, 0] * np.sin(k * xs))
+    pi_ = 2 * np.mean(i.u[:, 0] * np.sin(k * i.X[:, 0] * w.dx[0]))
+    assert abs((pe_ + M * pi_) - d) < 2e-2 * d
+
+
+def test_two_species_energy_uses_the_mass():
+    """Kinetic energy sums (q / (q/m)) (gamma - 1): over the two-species
+    oscillation field + kinetic energy stays within 1 % of its initial value
+    at dt = 0.1 x Courant (the diagnostic pairs u^{n-1/2} with E^n, an
+    O(omega dt) offset; weighting the ions by |q| instead of their mass
+    would be ~20 % off)."""
+    M = 4.0
+    w = I.WORKLOADS["w2d_64_linear"].with_(u_th=0.0, courant_fraction=0.1)
+    c, s = _two_species(w, M)
+    e, _ = s.species
+    k = 2 * np.pi / (w.n[0] * w.dx[0])
+    e.u[:, 0] = 1e-2 * np.sin(k * e.X[:, 0] * w.dx[0])
+    wf0, wk0 = s.energies()
+    W0 = wf0 + wk0
+    dev = 0.0
+    for _ in range(300):
+        s.step(1)
+        wf, wk = s.energies()
+        dev = max(dev, abs(wf + wk - W0))
+    assert dev < 1e-2 * W0
+
+
+def test_ion_kick_in_uniform_field():
+    """A zero-weight ion (q = 0, so no self field) of q/m = Z/M in a uniform
+    E: one Boris step changes u by exactly (q/m) E dt."""
+    c = cfg2(n=(8, 8), order=2)
+    E = np.zeros((3,) + c.shape)
+    E[0] = 0.3
+    E[1] = -0.7
+    B = np.zeros_like(E)
+    qm = 2.0 / 7.0
+    sp = O.Species(qm, np.array([[3.3, 4.6, 0.0]]), np.zeros((1, 3)), np.zeros(1))
+    s = O.MultiState(c, [sp], E, B)
+    s.step(1)
+    np.testing.assert_allclose(sp.u[0], [qm * 0.3 * c.dt, -qm * 0.7 * c.dt, 0.0], rtol=1e-14)
+
+
+@pytest.mark.parametrize("dims", [2, 3])
+def test_two_species_continuity_and_gauss(dims):
+    """Thermal electrons and ions: the total current (sum of the species'
+    currents) satisfies discrete continuity with the total charge density at
+    every interior node, and Gauss's law keeps its initial residual."""
+    if dims == 2:
+        w = I.Workload("t", 2, (20, 18), (0.2, 0.25), 2, 4, 0.3, 1, bc=(0, 1), seed=17)
+    else:
+        w = I.Workload("t", 3, (10, 9, 8), (0.2, 0.25, 0.3), 3, 2, 0.3, 1, bc=(0, 0, 1), seed=18)
+    w = w.with_(ions=I.Ions(mass_ratio=9.0, u_th=0.1))
+    wi = w
+    pe, pi = I.make_plasma(w), I.make_ions(wi)
+    E, B = I.laser_fields(w)
+    c = O.Config(w.dims, w.n3, w.dx3, w.dt, w.order, w.bc3)
+    s = O.MultiState(c, [O.Species(-1.0, pe.global_positions(w), pe.u.T, pe.charges()),
+                         O.Species(1.0 / 9.0, pi.global_positions(w), pi.u.T, pi.charges())], E, B)
+    mask = O.interior_mask(c)
+    g0 = O.divergence(c, s.E) - s.rho()
+    for _ in range(6):
+        r0 = s.rho()
+        s.step(1)
+        r1 = s.rho()
+        res = O.continuity_residual(c, r0, r1, s.J)
+        assert np.abs(res[mask]).max() < 1e-11 * (np.abs(r1 - r0).max() / c.dt)
+    g = O.divergence(c, s.E) - s.rho() - g0
+    assert np.abs(g[mask]).max() < 1e-11 * np.abs(s.rho()).max() + 1e-13
+
