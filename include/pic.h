@@ -77,7 +77,7 @@ typedef struct {
   int32_t n[3];       /* nodes (= cells) per axis, n[2] = 1 in 2D; each >= 2 (>= 4 if open) */
   double dx[3];       /* cell sizes, > 0 */
   double dt;          /* time step, 0 < dt <= Courant limit */
-  int32_t order;      /* B-spline interpolation/deposit order, 1..3 */
+  int32_t order;      /* B-spline interpolation/deposit order, 1..4 (Table 3) */
   int32_t real_bytes; /* 4 (FP32 offsets, momenta, fields) or 8 (FP64) */
   int32_t bc[3];      /* pic_bc per axis (ignored for z in 2D) */
   int32_t tile[3];    /* cells per tile per axis; 0 selects the default */

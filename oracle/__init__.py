@@ -111,7 +111,7 @@ def _ptr(a):
 def shape(order: int, X: float):
     """Order-n B-spline weights at X: (first node index, weights)."""
     base = np.zeros(1, dtype=np.int64)
-    w = np.zeros(4, dtype=np.float64)
+    w = np.zeros(5, dtype=np.float64)  # up to order 4
     lib().oracle_shape(order, float(X), _ptr(base), _ptr(w))
     return int(base[0]), w[: order + 1].copy()
 

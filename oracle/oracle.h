@@ -38,7 +38,7 @@ typedef struct {
   int32_t n[3];     /* cells (= nodes) per axis; n[2] = 1 in 2D */
   double dx[3];     /* cell size per axis, in c/omega_p */
   double dt;        /* time step, in 1/omega_p */
-  int32_t order;    /* B-spline order 1..3 */
+  int32_t order;    /* B-spline order 1..4 */
   int32_t bc[3];    /* ORACLE_PERIODIC or ORACLE_OPEN per axis */
   double q_over_m;  /* charge-to-mass ratio of the species (-1 for electrons) */
 } oracle_config;

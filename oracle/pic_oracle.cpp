@@ -115,11 +115,25 @@ inline long stencil_base(int order, double X) {
   return piece_index(order, X) - order / 2;
 }
 
-// B-spline weights of order 1..3 on the nodes base..base+order, evaluated at
+// B-spline weights of order 1..4 on the nodes base..base+order, evaluated at
 // X (the polynomial piece belonging to that stencil; used also at the closed
-// ends of the piece, where the spline is continuous).
+// ends of the piece, where the spline is continuous).  Order 4 is the quartic
+// spline of Table 3's fourth benchmark: with t = X - (base + 2), the distance
+// to the centre node, the five weights are the quartic B-spline at distances
+// t + 2, t + 1, t, 1 - t, 2 - t.
 template <class R>
 void shape_on_base(int order, R X, long base, R* w) {
+  if (order == 4) {
+    R t = X - (double)(base + 2);
+    R t2 = t * t, t3 = t2 * t, t4 = t2 * t2;
+    R a = 1.0 - 2.0 * t, b = 1.0 + 2.0 * t;
+    w[0] = a * a * a * a / 384.0;
+    w[1] = (19.0 - 44.0 * t + 24.0 * t2 + 16.0 * t3 - 16.0 * t4) / 96.0;
+    w[2] = (115.0 - 120.0 * t2 + 48.0 * t4) / 192.0;
+    w[3] = (19.0 + 44.0 * t + 24.0 * t2 - 16.0 * t3 - 16.0 * t4) / 96.0;
+    w[4] = b * b * b * b / 384.0;
+    return;
+  }
   if (order == 1) {
     R t = X - (double)base;
     w[0] = 1.0 - t;
@@ -147,7 +161,7 @@ void shape_on_base(int order, R X, long base, R* w) {
 template <class R>
 R interp(const Grid& g, const R* F, const int st[3], const R X[3]) {
   long base[3];
-  R w[3][4];
+  R w[3][5];
   int cnt[3];
   for (int d = 0; d < 3; ++d) {
     if (d < g.dims) {
@@ -272,11 +286,11 @@ void deposit_path(const Grid& g, R* J, const R X0[3], const R X1[3], double q,
     R ftime = tpar[s + 1] - tpar[s];
     if (!(val(ftime) > 0.0)) continue;  // equal crossings: zero-length segment
     long base[3];
-    R S0[3][4], dS[3][4];
+    R S0[3][5], dS[3][5];
     for (int d = 0; d < D; ++d) {
       double mid = 0.5 * (val(Xa[d]) + val(Xb[d]));
       base[d] = stencil_base(ord, mid);
-      R S1[4];
+      R S1[5];
       shape_on_base(ord, Xa[d], base[d], S0[d]);
       shape_on_base(ord, Xb[d], base[d], S1);
       for (int i = 0; i < m; ++i) dS[d][i] = S1[i] - S0[d][i];
@@ -666,7 +680,7 @@ void oracle_deposit_rho(const oracle_config* cfg, int64_t np, const double* X,
   for (long p = 0; p < np; ++p) {
     if (!alive[p]) continue;
     long base[3] = {0, 0, 0};
-    double w[3][4] = {{1, 0, 0, 0}, {1, 0, 0, 0}, {1, 0, 0, 0}};
+    double w[3][5] = {{1, 0, 0, 0, 0}, {1, 0, 0, 0, 0}, {1, 0, 0, 0, 0}};
     int cnt[3] = {1, 1, 1};
     for (int d = 0; d < g.dims; ++d) {
       base[d] = stencil_base(g.order, X[3 * p + d]);

@@ -26,12 +26,19 @@ __device__ __forceinline__ void shape_deriv(R xi, R* d) {
     d[0] = xi - R(0.5);
     d[1] = R(-2) * xi;
     d[2] = R(0.5) + xi;
-  } else {
+  } else if (ORDER == 3) {
     const R s = R(1) - xi;
     d[0] = R(-0.5) * s * s;
     d[1] = xi * (R(1.5) * xi - R(2));
     d[2] = R(0.5) + xi - R(1.5) * xi * xi;
     d[3] = R(0.5) * xi * xi;
+  } else {
+    const R a = R(1) - R(2) * xi, b = R(1) + R(2) * xi;
+    d[0] = R(-1.0 / 48.0) * a * a * a;
+    d[1] = R(1.0 / 96.0) * (R(-44) + xi * (R(48) + xi * (R(48) - R(64) * xi)));
+    d[2] = xi * (R(-1.25) + xi * xi);
+    d[3] = R(1.0 / 96.0) * (R(44) + xi * (R(48) + xi * (R(-48) - R(64) * xi)));
+    d[4] = R(1.0 / 48.0) * b * b * b;
   }
 }
 
@@ -473,7 +480,8 @@ int launch_push_deposit_adjoint(const pic_ctx* ctx, const pic_particles* p, cons
   if (D == DD && O == OO)                                                        \
     return dbl ? launch_pda<DD, OO, double>(ctx, p, f, lam_f, lam_p, ws, s)     \
                : launch_pda<DD, OO, float>(ctx, p, f, lam_f, lam_p, ws, s);
-  PIC_PDA(2, 1) PIC_PDA(2, 2) PIC_PDA(2, 3) PIC_PDA(3, 1) PIC_PDA(3, 2) PIC_PDA(3, 3)
+  PIC_PDA(2, 1) PIC_PDA(2, 2) PIC_PDA(2, 3) PIC_PDA(2, 4)
+  PIC_PDA(3, 1) PIC_PDA(3, 2) PIC_PDA(3, 3) PIC_PDA(3, 4)
 #undef PIC_PDA
   return (int)hipErrorInvalidValue;
 }

@@ -39,12 +39,19 @@ __device__ __forceinline__ int node_weights(double o, double* w) {
     w[0] = 0.5 * a * a;
     w[1] = 0.75 - xi * xi;
     w[2] = 0.5 * b * b;
-  } else {
+  } else if (ORDER == 3) {
     const double s = 1.0 - xi, t2 = xi * xi, t3 = t2 * xi;
     w[0] = s * s * s / 6.0;
     w[1] = (4.0 - 6.0 * t2 + 3.0 * t3) / 6.0;
     w[2] = (1.0 + 3.0 * xi + 3.0 * t2 - 3.0 * t3) / 6.0;
     w[3] = t3 / 6.0;
+  } else {
+    const double a = 1.0 - 2.0 * xi, b = 1.0 + 2.0 * xi, t2 = xi * xi;
+    w[0] = a * a * a * a / 384.0;
+    w[1] = (19.0 + xi * (-44.0 + xi * (24.0 + xi * (16.0 - 16.0 * xi)))) / 96.0;
+    w[2] = (115.0 + t2 * (-120.0 + 48.0 * t2)) / 192.0;
+    w[3] = (19.0 + xi * (44.0 + xi * (24.0 + xi * (-16.0 - 16.0 * xi)))) / 96.0;
+    w[4] = b * b * b * b / 384.0;
   }
   return k - ORDER / 2;
 }
@@ -250,7 +257,8 @@ int launch_deposit_rho(const pic_ctx* ctx, const pic_particles* p, double* rho, 
     else                                                             \
       rho_t<DD, OO, float>(P, p, qc, rho, s);                        \
   }
-  PIC_RHO(2, 1) PIC_RHO(2, 2) PIC_RHO(2, 3) PIC_RHO(3, 1) PIC_RHO(3, 2) PIC_RHO(3, 3)
+  PIC_RHO(2, 1) PIC_RHO(2, 2) PIC_RHO(2, 3) PIC_RHO(2, 4)
+  PIC_RHO(3, 1) PIC_RHO(3, 2) PIC_RHO(3, 3) PIC_RHO(3, 4)
 #undef PIC_RHO
   return (int)hipGetLastError();
 }

@@ -48,13 +48,21 @@ __device__ __forceinline__ void shape(R xi, R* w) {
     w[0] = R(0.5) * a * a;
     w[1] = R(0.75) - xi * xi;
     w[2] = R(0.5) * b * b;
-  } else {
+  } else if (ORDER == 3) {
     const R s = R(1) - xi, t2 = xi * xi, t3 = t2 * xi;
     const R sixth = R(1.0 / 6.0);
     w[0] = sixth * s * s * s;
     w[1] = sixth * (R(4) - R(6) * t2 + R(3) * t3);
     w[2] = sixth * (R(1) + R(3) * xi + R(3) * t2 - R(3) * t3);
     w[3] = sixth * t3;
+  } else {  // quartic: xi is the distance to the centre node of the piece
+    const R a = R(1) - R(2) * xi, b = R(1) + R(2) * xi;
+    const R a2 = a * a, b2 = b * b, t2 = xi * xi;
+    w[0] = R(1.0 / 384.0) * a2 * a2;
+    w[1] = R(1.0 / 96.0) * (R(19) + xi * (R(-44) + xi * (R(24) + xi * (R(16) - R(16) * xi))));
+    w[2] = R(1.0 / 192.0) * (R(115) + t2 * (R(-120) + R(48) * t2));
+    w[3] = R(1.0 / 96.0) * (R(19) + xi * (R(44) + xi * (R(24) + xi * (R(-16) - R(16) * xi))));
+    w[4] = R(1.0 / 384.0) * b2 * b2;
   }
 }
 
@@ -72,7 +80,7 @@ __device__ __forceinline__ void dshape(R xa, R xb, R* d) {
     d[0] = R(-0.5) * dl * (R(1) - s);
     d[1] = -dl * s;
     d[2] = R(0.5) * dl * (R(1) + s);
-  } else {
+  } else if (ORDER == 3) {
     const R sixth = R(1.0 / 6.0);
     const R s = xa + xb;
     const R Q = xa * xa + xa * xb + xb * xb;
@@ -81,6 +89,16 @@ __device__ __forceinline__ void dshape(R xa, R xb, R* d) {
     d[1] = sixth * dl * (R(-6) * s + R(3) * Q);
     d[2] = sixth * dl * (R(3) + R(3) * s - R(3) * Q);
     d[3] = sixth * dl * Q;
+  } else {  // quartic: divided differences of the five polynomials
+    const R s1 = xa + xb, sq = xa * xa + xb * xb;
+    const R s2 = sq + xa * xb, s3 = s1 * sq;
+    const R A = R(1) - R(2) * xa, B = R(1) - R(2) * xb;
+    const R C = R(1) + R(2) * xa, D = R(1) + R(2) * xb;
+    d[0] = R(-1.0 / 192.0) * dl * ((A + B) * (A * A + B * B));
+    d[1] = R(1.0 / 96.0) * dl * (R(-44) + R(24) * s1 + R(16) * s2 - R(16) * s3);
+    d[2] = R(0.125) * dl * s1 * (R(-5) + R(2) * sq);
+    d[3] = R(1.0 / 96.0) * dl * (R(44) + R(24) * s1 - R(16) * s2 - R(16) * s3);
+    d[4] = R(1.0 / 192.0) * dl * ((C + D) * (C * C + D * D));
   }
 }
 

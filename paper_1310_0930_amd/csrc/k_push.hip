@@ -372,7 +372,8 @@ int launch_push_deposit(const pic_ctx* ctx, const pic_particles* p, const pic_fi
   if (D == DD && O == OO)                                                         \
     return dbl ? launch_pd<DD, OO, double>(ctx, p, f, ws, s, accumulate)         \
                : launch_pd<DD, OO, float>(ctx, p, f, ws, s, accumulate);
-  PIC_PD(2, 1) PIC_PD(2, 2) PIC_PD(2, 3) PIC_PD(3, 1) PIC_PD(3, 2) PIC_PD(3, 3)
+  PIC_PD(2, 1) PIC_PD(2, 2) PIC_PD(2, 3) PIC_PD(2, 4)
+  PIC_PD(3, 1) PIC_PD(3, 2) PIC_PD(3, 3) PIC_PD(3, 4)
 #undef PIC_PD
   return (int)hipErrorInvalidValue;
 }

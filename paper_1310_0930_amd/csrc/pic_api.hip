@@ -104,7 +104,8 @@ static int kernel_geometry(const pic_config* c, int* T, int* A, size_t* lds) {
       geo_of<DD, OO, float>(T, A, lds);                                 \
     return 0;                                                           \
   }
-  PIC_GEO(2, 1) PIC_GEO(2, 2) PIC_GEO(2, 3) PIC_GEO(3, 1) PIC_GEO(3, 2) PIC_GEO(3, 3)
+  PIC_GEO(2, 1) PIC_GEO(2, 2) PIC_GEO(2, 3) PIC_GEO(2, 4)
+  PIC_GEO(3, 1) PIC_GEO(3, 2) PIC_GEO(3, 3) PIC_GEO(3, 4)
 #undef PIC_GEO
   return -1;
 }
@@ -118,7 +119,7 @@ static bool finite_pos(double v) { return isfinite(v) && v > 0.0; }
 static int validate_config(const pic_config* c) {
   if (!c) return PIC_EINVAL;
   if (c->dims != 2 && c->dims != 3) return PIC_EINVAL;
-  if (c->order < 1 || c->order > 3) return PIC_EINVAL;
+  if (c->order < 1 || c->order > 4) return PIC_EINVAL;
   if (c->real_bytes != 4 && c->real_bytes != 8) return PIC_EINVAL;
   if (c->sort_every < 1) return PIC_EINVAL;
   if (!isfinite(c->q_over_m) || !isfinite(c->q_const)) return PIC_EINVAL;

@@ -15,10 +15,10 @@ namespace pic {
 // (larger moves take the global-memory path).
 template <int ORDER>
 struct Reach {
-  static constexpr int g_lo = ORDER == 3 ? -2 : -1;
-  static constexpr int g_hi = ORDER == 1 ? 1 : 2;
-  static constexpr int d_lo = ORDER == 3 ? -2 : -1;
-  static constexpr int d_hi = ORDER == 3 ? 3 : 2;
+  static constexpr int g_lo = ORDER >= 3 ? -2 : -1;
+  static constexpr int g_hi = ORDER == 1 ? 1 : ORDER == 4 ? 3 : 2;
+  static constexpr int d_lo = ORDER >= 3 ? -2 : -1;
+  static constexpr int d_hi = ORDER >= 3 ? 3 : 2;
 };
 
 // Tile shape (cells per axis) and drift allowance A: one workgroup owns the
@@ -29,7 +29,8 @@ struct Reach {
 // instruction.
 template <int DIMS, int ORDER, typename R>
 struct Geo {
-  static constexpr bool big = (sizeof(R) == 8 && ORDER == 3);
+  // large stencils: no drift allowance in 3D (the LDS regions would not fit)
+  static constexpr bool big = ORDER == 4 || (sizeof(R) == 8 && ORDER == 3);
   static constexpr int T = DIMS == 3 ? 8 : 16;
   static constexpr int TZ = DIMS == 3 ? T : 1;
   static constexpr int A = DIMS == 3 ? (big ? 0 : 1) : 2;
@@ -59,7 +60,7 @@ struct Geo {
   // brings all the wavefronts: 16 (4 per SIMD, <= 128 VGPRs) in FP32, 8 in
   // FP64 whose gather and deposit need more registers; 2D tiles are small
   // and several workgroups share a CU
-  static constexpr int NT = DIMS == 2 ? 256 : (sizeof(R) == 4 ? 1024 : 512);
+  static constexpr int NT = DIMS == 2 ? 256 : (sizeof(R) == 4 && ORDER <= 3 ? 1024 : 512);
 };
 
 // Unsigned division by a runtime divisor through a precomputed multiplier

@@ -54,7 +54,7 @@ def _good(**kw):
 
 @pytest.mark.parametrize("kw,expect", [
     (dict(dims=1), P.PIC_EINVAL),
-    (dict(order=4), P.PIC_EINVAL),
+    (dict(order=5), P.PIC_EINVAL),
     (dict(order=0), P.PIC_EINVAL),
     (dict(real_bytes=2), P.PIC_EINVAL),
     (dict(n=(1, 128, 128)), P.PIC_EINVAL),

@@ -112,7 +112,7 @@ def _one_step_check(w, rb, seed):
     return lhs, rhs
 
 
-@pytest.mark.parametrize("order", [1, 2, 3])
+@pytest.mark.parametrize("order", [1, 2, 3, 4])
 def test_step_adjoint_matches_oracle_jvp_3d(order):
     w = I.Workload("adj3", 3, (12, 10, 9), (0.2, 0.25, 0.2), order, 4, 0.3, 1,
                    seed=I.SEED_BASE + 90 + order)
@@ -120,7 +120,7 @@ def test_step_adjoint_matches_oracle_jvp_3d(order):
     assert abs(lhs - rhs) <= 1e-10 * abs(lhs)
 
 
-@pytest.mark.parametrize("order", [1, 2, 3])
+@pytest.mark.parametrize("order", [1, 2, 3, 4])
 def test_step_adjoint_matches_oracle_jvp_2d_open_laser(order):
     lz = I.Laser(a0=2.0, omega0=4.0, waist=1.0, tau=0.4, x_center=1.2)
     w = I.Workload("adj2", 2, (32, 16), (0.1, 0.2), order, 4, 0.2, 1, bc=(0, 1),

@@ -51,7 +51,7 @@ def test_parity_2d_linear_64(rb):
 
 
 @pytest.mark.parametrize("rb", [8, 4])
-@pytest.mark.parametrize("order", [1, 2, 3])
+@pytest.mark.parametrize("order", [1, 2, 3, 4])
 def test_parity_3d_small(rb, order):
     """3D periodic, thermal 0.05, ragged grid (not a multiple of the tile),
     re-sorted every 3 steps."""
@@ -62,7 +62,7 @@ def test_parity_3d_small(rb, order):
 
 
 @pytest.mark.parametrize("rb", [8, 4])
-@pytest.mark.parametrize("order", [2, 3])
+@pytest.mark.parametrize("order", [2, 3, 4])
 def test_parity_2d_orders(rb, order):
     w = I.Workload("w2d_small", 2, (40, 36), (0.2, 0.15), order, 9, 0.1, 12,
                    seed=I.SEED_BASE + 30 + order)
@@ -71,16 +71,17 @@ def test_parity_2d_orders(rb, order):
 
 
 @pytest.mark.parametrize("rb", [8, 4])
-def test_parity_3d_cubic_open_laser(rb):
-    """Cubic shapes, cold plasma with a density ramp, a0 = 4 laser, open y and
-    z (Mur fields, absorbed particles): the recipe of the 256x128x128 workload
-    on a smaller box."""
+@pytest.mark.parametrize("order", [3, 4])
+def test_parity_3d_cubic_open_laser(rb, order):
+    """Cubic (and quartic) shapes, cold plasma with a density ramp, a0 = 4
+    laser, open y and z (Mur fields, absorbed particles): the recipe of the
+    256x128x128 workload on a smaller box."""
     lz = I.Laser(a0=4.0, omega0=10.0, waist=1.5, tau=0.6, x_center=1.8)
-    w = I.Workload("w3d_cubic_open", 3, (48, 20, 20), (0.1, 0.2, 0.2), 3, 2, 0.0, 12,
+    w = I.Workload("w3d_cubic_open", 3, (48, 20, 20), (0.1, 0.2, 0.2), order, 2, 0.0, 12,
                    bc=(I.PERIODIC, I.OPEN, I.OPEN), ramp_cells=20.0, laser=lz,
                    seed=I.SEED_BASE + 40)
     sim, ref = _run(w, rb, w.steps, sort_every=4)
-    _check(compare(w, sim, ref), rb, "3d cubic open laser")
+    _check(compare(w, sim, ref), rb, f"3d order {order} open laser")
 
 
 def _w2d_open(steps):

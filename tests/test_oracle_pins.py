@@ -29,7 +29,7 @@ def cfg2(n=(16, 16), dx=(0.2, 0.2), order=1, bc=(0, 0), frac=0.5):
 
 
 # ---------------------------------------------------------------- shapes
-@pytest.mark.parametrize("order", [1, 2, 3])
+@pytest.mark.parametrize("order", [1, 2, 3, 4])
 def test_shape_matches_cardinal_bspline(order):
     """Weights equal the centred cardinal B-spline of degree `order`
     (scipy's basis element on knots -(n+1)/2 .. (n+1)/2)."""
@@ -45,7 +45,7 @@ def test_shape_matches_cardinal_bspline(order):
             assert abs(np.nan_to_num(M(X - far))) < 1e-14
 
 
-@pytest.mark.parametrize("order", [1, 2, 3])
+@pytest.mark.parametrize("order", [1, 2, 3, 4])
 def test_shape_moments(order):
     for X in RNG.uniform(0, 50, size=100):
         base, w = O.shape(order, X)
@@ -54,7 +54,7 @@ def test_shape_moments(order):
         assert abs(np.dot(base + np.arange(order + 1), w) - X) < 1e-12
 
 
-@pytest.mark.parametrize("order", [1, 2, 3])
+@pytest.mark.parametrize("order", [1, 2, 3, 4])
 def test_gather_reproduces_linear_fields(order):
     """B-splines reproduce linear functions, at node-centred and staggered
     component positions alike (each component sampled where it sits)."""
@@ -335,7 +335,7 @@ def _rho_of(c, X, q):
 
 
 @pytest.mark.parametrize("dims", [2, 3])
-@pytest.mark.parametrize("order", [1, 2, 3])
+@pytest.mark.parametrize("order", [1, 2, 3, 4])
 def test_deposit_discrete_continuity(dims, order):
     """(rho(X1) - rho(X0))/dt + D.J = 0 node by node, for paths that cross
     0, 1, 2 or 3 stencil-switch planes (the reason for the split)."""
@@ -348,7 +348,7 @@ def test_deposit_discrete_continuity(dims, order):
     assert np.abs(r).max() < 1e-12 * scale
 
 
-@pytest.mark.parametrize("order", [1, 2, 3])
+@pytest.mark.parametrize("order", [1, 2, 3, 4])
 def test_deposit_total_current_and_antisymmetry(order):
     """Summed over the grid, J_d = q dx_d (X1-X0)_d / dt (the current of a
     point charge); swapping the ends negates J."""
@@ -439,7 +439,8 @@ def _thermal_state(w, quiet=False):
 
 
 @pytest.mark.parametrize("dims,order,bc", [(2, 1, (0, 0)), (2, 2, (0, 1)), (3, 2, (0, 0, 0)),
-                                           (3, 3, (0, 1, 1)), (3, 1, (1, 0, 1))])
+                                           (3, 3, (0, 1, 1)), (3, 1, (1, 0, 1)), (2, 4, (0, 1)),
+                                           (3, 4, (0, 0, 1))])
 def test_step_continuity_and_gauss(dims, order, bc):
     """Whole steps: discrete continuity holds to round-off at every interior
     node, hence Gauss's law D.E - rho keeps its initial value."""
