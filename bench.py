@@ -30,14 +30,15 @@ METRIC = "particle pushes/sec (interp+push+deposit) and % HBM roofline, FP32 vs 
 
 
 def algorithmic_bytes(w, np_, real_bytes):
-    """Bytes the push/deposit must move per launch: particle state read and
+    """Bytes the push/deposit must move per step: particle state read and
     written once (cell + D offsets + 3 momenta, + q when per-particle), one
-    read of E and B and one write of J per cell."""
+    read of E and B and one write of J per cell for every species."""
     per_particle = 2 * (4 + real_bytes * (w.dims + 3))
     if w.ramp_cells > 0:
         per_particle += real_bytes
     per_cell = 9 * real_bytes
-    return np_ * per_particle + w.ncell * per_cell
+    nspecies = 1 if w.ions is None else 2
+    return np_ * per_particle + w.ncell * per_cell * nspecies
 
 
 def kernel_hash():
@@ -67,15 +68,22 @@ def run_gpu(w, real_bytes, steps, warmup, log):
     sim = Simulation.from_workload(w, real_bytes=real_bytes)
     sim.load(pl, E, B, with_id=False)
     del pl
+    if w.ions is not None:  # mobile ions: a second species in the same fields
+        sim.add_species(I.make_ions(w), w.ions.q_over_m, w.q_const_ions, with_id=False)
+    everyone = [sim] + sim.species
+    np_total = sum(s.np for s in everyone)
     torch.cuda.synchronize()
-    log(f"loaded {w.name} np={sim.np} real={real_bytes}")
+    log(f"loaded {w.name} np={np_total} ({len(everyone)} species) real={real_bytes}")
 
     def one_step(k, ev=None):
         if k % w.sort_every == 0:
-            sim.sort()
+            for s in everyone:
+                s.sort()
         if ev is not None:
             ev[0].record()
         sim.push_deposit()
+        for s in sim.species:
+            s.push_deposit_add()
         if ev is not None:
             ev[1].record()
         sim.field_advance()
@@ -97,12 +105,16 @@ def run_gpu(w, real_bytes, steps, warmup, log):
     wall = time.perf_counter() - wall0
     total_ms = t0.elapsed_time(t1)
     push_ms = [a.elapsed_time(b) for a, b in evs]
-    flags, nslow = sim.read_flags()
+    flags, nslow = 0, 0
+    for s in everyone:
+        f_, n_ = s.read_flags()
+        flags |= f_
+        nslow += n_
     diag = sim.diagnostics()
     log(f"{w.name} real={real_bytes}: {total_ms / steps:.3f} ms/step, push {np.mean(push_ms):.3f} ms, "
         f"slow={nslow} flags={flags}")
     return {
-        "np": sim.np, "ms_per_step": total_ms / steps, "wall_s": wall,
+        "np": np_total, "ms_per_step": total_ms / steps, "wall_s": wall,
         "push_ms_mean": float(np.mean(push_ms)), "push_ms_median": float(np.median(push_ms)),
         "slowpath": int(nslow), "flags": int(flags), "n_alive": int(diag.raw["n_alive"]),
     }
@@ -199,6 +211,7 @@ def main():
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": w.name, "dims": w.dims, "grid": list(w.n3), "dx": list(w.dx3),
                    "ppc": w.ppc, "particles": r32["np"], "order": w.order, "u_th": w.u_th,
+                   "species": 1 if w.ions is None else 2,
                    "dt": w.dt, "sort_every": w.sort_every, "boundaries": list(w.bc3),
                    "parallelism": "single GPU"},
         "push_deposit_pushes_per_s": r32["np"] / (r32["push_ms_mean"] * 1e-3),

@@ -29,22 +29,25 @@ struct Reach {
 // instruction.
 template <int DIMS, int ORDER, typename R>
 struct Geo {
-  // large stencils: no drift allowance in 3D (the LDS regions would not fit)
-  static constexpr bool big = ORDER == 4 || (sizeof(R) == 8 && ORDER == 3);
-  static constexpr int T = DIMS == 3 ? 8 : 16;
-  static constexpr int TZ = DIMS == 3 ? T : 1;
-  static constexpr int A = DIMS == 3 ? (big ? 0 : 1) : 2;
+  // 3D tiles are 8^3 cells with one cell of drift allowance; the largest
+  // stencils halve the tile along z (quartic, and cubic in double
+  // precision), and along every axis for quartic in double precision, so
+  // that the allowance stays and the LDS regions still fit a CU
+  static constexpr bool wide = ORDER == 4 || (sizeof(R) == 8 && ORDER == 3);
+  static constexpr int T = DIMS == 3 ? ((ORDER == 4 && sizeof(R) == 8) ? 4 : 8) : 16;
+  static constexpr int TZ = DIMS == 3 ? (wide ? 4 : T) : 1;
+  static constexpr int A = DIMS == 3 ? 1 : 2;
   static constexpr int AZ = DIMS == 3 ? A : 0;
   using Rc = Reach<ORDER>;
   // E/B region
   static constexpr int ex = T + 2 * A + Rc::g_hi - Rc::g_lo;
-  static constexpr int ez = DIMS == 3 ? ex : 1;
+  static constexpr int ez = DIMS == 3 ? TZ + 2 * AZ + Rc::g_hi - Rc::g_lo : 1;
   static constexpr int e_lo = -A + Rc::g_lo;  // region origin relative to the tile origin
   static constexpr int e_lo_z = DIMS == 3 ? e_lo : 0;
   static constexpr int e_vol = ex * ex * ez;
   // J region
   static constexpr int jx = T + 2 * A + Rc::d_hi - Rc::d_lo;
-  static constexpr int jz = DIMS == 3 ? jx : 1;
+  static constexpr int jz = DIMS == 3 ? TZ + 2 * AZ + Rc::d_hi - Rc::d_lo : 1;
   static constexpr int j_lo = -A + Rc::d_lo;
   static constexpr int j_lo_z = DIMS == 3 ? j_lo : 0;
   static constexpr int j_vol = jx * jx * jz;
@@ -57,9 +60,9 @@ struct Geo {
   static constexpr bool fixed = sizeof(R) == 4;
   static constexpr size_t lds_bytes = sizeof(R) * 6 * (size_t)e_vol + sizeof(double) * 3 * (size_t)j_vol;
   // threads per workgroup: in 3D one workgroup fills a CU's LDS, so it
-  // brings all the wavefronts: 16 (4 per SIMD, <= 128 VGPRs) in FP32, 8 in
-  // FP64 whose gather and deposit need more registers; 2D tiles are small
-  // and several workgroups share a CU
+  // brings all the wavefronts: 16 (4 per SIMD, <= 128 VGPRs) in FP32 up to
+  // cubic order, 8 for FP64 and quartic, whose gather and deposit need more
+  // registers; 2D tiles are small and several workgroups share a CU
   static constexpr int NT = DIMS == 2 ? 256 : (sizeof(R) == 4 && ORDER <= 3 ? 1024 : 512);
 };
 

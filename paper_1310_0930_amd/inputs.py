@@ -148,6 +148,15 @@ WORKLOADS = {
                                         (0.1, 0.2, 0.2), 2, 8, 0.0, 100, laser=Laser(),
                                         sort_every=20, seed=SEED_BASE + 5),
 }
+# The 128^3 warm-plasma recipe at the other orders of Table 3 (linear, cubic,
+# quartic), and with a mobile ion species (hydrogen mass ratio, thermal
+# spread 0.05 / sqrt(1836) for equal temperatures).
+for _o, _name in ((1, "linear"), (3, "cubic"), (4, "quartic")):
+    WORKLOADS[f"w3d_128_{_name}"] = WORKLOADS["w3d_128_quadratic"].with_(
+        name=f"w3d_128_{_name}", order=_o, seed=SEED_BASE + 10 + _o)
+WORKLOADS["w3d_128_quadratic_ions"] = WORKLOADS["w3d_128_quadratic"].with_(
+    name="w3d_128_quadratic_ions", ions=Ions(mass_ratio=1836.15, u_th=0.05 / math.sqrt(1836.15)),
+    seed=SEED_BASE + 6)
 
 
 def _round32(a):

@@ -393,6 +393,9 @@ class Simulation:
     def push_deposit(self):
         pic_push_deposit(self.ctx, self._parts, self._fields, self.ws.data_ptr(), self.stream)
 
+    def push_deposit_add(self):
+        pic_push_deposit_add(self.ctx, self._parts, self._fields, self.ws.data_ptr(), self.stream)
+
     def field_advance(self):
         pic_field_advance(self.ctx, self._fields, self.ws.data_ptr(), self.stream)
 
