@@ -119,6 +119,31 @@ typedef struct {
   int64_t n_slowpath;   /* particle pushes that took the global-memory path */
 } pic_diag;
 
+/* Particles entering the front column of a moving window (see
+ * pic_window_shift): n = ppc per particle cell of the column, the column's
+ * cells in storage order (y fastest, then z), ppc consecutive particles per
+ * cell.  Device arrays of the working precision, caller-owned; the random
+ * draws of a plasma injection are inputs, not drawn by the library. */
+typedef struct {
+  int64_t n;         /* particles to append (0: vacuum ahead) */
+  int32_t ppc;       /* particles per column cell (n = ppc * column cells) */
+  const void* off[3];  /* offsets in [0,1) (all dims, x included) */
+  const void* u[3];    /* momenta */
+  const void* q;       /* charges, required when the particles carry q, else NULL */
+} pic_inject;
+
+/* Laser antenna: a sheet of current on the plane of E-samples x = x_index
+ * (node index along x) that radiates a pulse of peak field a0*omega0 both
+ * ways (a current sheet K radiates E = -K/2): J_pol += -2 a0 omega0 env(t)
+ * g(y, z) cos(omega0 (t - t_center)) / dx, with env = exp(-(t-t_center)^2 /
+ * tau^2) cut beyond 3 tau and g = exp(-r^2/waist^2) about (y_center,
+ * z_center) (cell units times dx).  polarization: 1 = y, 2 = z. */
+typedef struct {
+  int32_t x_index;
+  int32_t polarization;
+  double a0, omega0, waist, tau, t_center, y_center, z_center;
+} pic_antenna;
+
 /* Validate `cfg` and create a context bound to the current HIP device.
  * Returns PIC_EINVAL / PIC_ECOURANT / PIC_ELDS for a bad configuration
  * (checked before any HIP call), PIC_EHIP if no device is usable.
@@ -199,6 +224,28 @@ int pic_diagnostics_species(int32_t nspecies, pic_ctx* const* ctx, const pic_par
                             void* const* ws, const pic_fields* f, const double* rho_prev,
                             const double* gauss_ref, double* rho_out, double* gauss_out,
                             pic_diag* out, void* stream);
+
+/* Moving window (Sec. 2: the simulation box follows the laser through the
+ * plasma): shift the state one cell toward -x.  E and B move one cell
+ * (F[i] <- F[i+1], the front plane zeroed), J is zeroed, every particle's
+ * cell moves one cell down in x (those leaving at x < 0 are absorbed), and
+ * `in->n` particles are appended in the front particle column (x = n0-2) from
+ * `in` (their id, if p->id, continues the count from p->np).  Requires an
+ * open x axis; `capacity` is the length of the particle arrays (PIC_EINVAL if
+ * p->np + in->n exceeds it).  Updates p->np; the particles must be sorted
+ * again before the next push.  f = NULL shifts only the particles (further
+ * species of a multi-species run, after the first species moved the fields). */
+int pic_window_shift(pic_ctx* ctx, pic_particles* p, int64_t capacity, pic_fields* f,
+                     const pic_inject* in, void* ws, void* stream);
+
+/* Add the antenna's current at time t to f->J (after the deposit, before
+ * the field advance: t is the time of J, (n + 1/2) dt). */
+int pic_antenna_add(pic_ctx* ctx, pic_fields* f, const pic_antenna* a, double t, void* stream);
+
+/* Attach an antenna to the context (copied; NULL detaches): pic_step and
+ * pic_step_species then add its current every step at t = (n + 1/2) dt, with
+ * n the context's step count. */
+int pic_set_antenna(pic_ctx* ctx, const pic_antenna* a);
 
 /* Transpose of pic_field_advance (hand-written adjoint; the advance is linear
  * in E, B, J).  In: lam->E, lam->B = adjoints of E^{n+1}, B^{n+1}.  Out, in

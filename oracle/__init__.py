@@ -167,6 +167,8 @@ class State:
         self.alive = np.ascontiguousarray(self.alive, dtype=np.int8).copy()
         if self.J is None:
             self.J = self.cfg.zeros_field()
+        self.nstep = 0          # steps taken (time of J: (nstep + 1/2) dt)
+        self.antenna = None     # Antenna, or None
 
     @property
     def np(self) -> int:
@@ -184,9 +186,17 @@ class State:
         lib().oracle_field_advance(C.byref(self.cfg.c()), _ptr(self.E), _ptr(self.B), _ptr(self.J))
 
     def step(self, nsteps: int = 1, nthreads: int = 1):
-        lib().oracle_step(C.byref(self.cfg.c()), self.np, _ptr(self.X), _ptr(self.u), _ptr(self.q),
-                          _ptr(self.alive), _ptr(self.E), _ptr(self.B), _ptr(self.J),
-                          int(nsteps), int(nthreads))
+        if self.antenna is None:
+            lib().oracle_step(C.byref(self.cfg.c()), self.np, _ptr(self.X), _ptr(self.u),
+                              _ptr(self.q), _ptr(self.alive), _ptr(self.E), _ptr(self.B),
+                              _ptr(self.J), int(nsteps), int(nthreads))
+            self.nstep += nsteps
+            return
+        for _ in range(nsteps):  # push, add the antenna's current, advance
+            self.push_deposit(nthreads)
+            self.J += antenna_current(self.cfg, self.antenna, (self.nstep + 0.5) * self.cfg.dt)
+            self.field_advance()
+            self.nstep += 1
 
     def step_jvp(self, nsteps, dX, du, dE, dB, dJ=None):
         """Advance in place and return the tangents (dX, du, dE, dB, dJ)."""
@@ -250,6 +260,8 @@ class MultiState:
         self.E = _f64(E).reshape((3,) + cfg.shape).copy()
         self.B = _f64(B).reshape((3,) + cfg.shape).copy()
         self.J = cfg.zeros_field()
+        self.nstep = 0
+        self.antenna = None
 
     def _cfg(self, sp: Species) -> _Cfg:
         c = self.cfg.c()
@@ -269,7 +281,10 @@ class MultiState:
     def step(self, nsteps: int = 1, nthreads: int = 1):
         for _ in range(nsteps):
             self.push_deposit(nthreads)
+            if self.antenna is not None:
+                self.J += antenna_current(self.cfg, self.antenna, (self.nstep + 0.5) * self.cfg.dt)
             self.field_advance()
+            self.nstep += 1
 
     def rho(self):
         """Total charge density (sum over species)."""
@@ -292,6 +307,77 @@ class MultiState:
                                   C.byref(wk))
             total_k += wk.value
         return wf.value, total_k
+
+
+# ---------------------------------------------------------------- window, antenna
+@dataclass
+class Antenna:
+    """A current sheet on the plane of E samples x = x_index that radiates a
+    laser pulse of peak field a0 omega0 both ways (polarization 1: y, 2: z)."""
+    x_index: int
+    polarization: int
+    a0: float
+    omega0: float
+    waist: float
+    tau: float
+    t_center: float
+    y_center: float
+    z_center: float = 0.0
+
+
+def antenna_current(cfg: Config, a: Antenna, t: float):
+    """Current of the antenna at time t, shape (3, n2, n1, n0).  In the
+    normalised Maxwell equations a sheet current K (per unit area) radiates
+    E = -K/2 on both sides, so K = -2 a0 omega0 env(t) g(y, z) cos(omega0 (t -
+    t_center)); on the grid the sheet occupies one cell along x: J = K/dx.
+    env = exp(-(t - t_center)^2/tau^2) (zero beyond 3 tau), g = exp(-r^2/w^2)
+    about (y_center, z_center), each sample at its own Yee position."""
+    J = cfg.zeros_field()
+    tr = t - a.t_center
+    if abs(tr) > 3.0 * a.tau:
+        return J
+    nz, ny, nx = cfg.shape
+    pol = a.polarization
+    y = (np.arange(ny) + (0.5 if pol == 1 else 0.0)) * cfg.dx[1] - a.y_center
+    if cfg.dims == 3:
+        z = (np.arange(nz) + (0.5 if pol == 2 else 0.0)) * cfg.dx[2] - a.z_center
+    else:
+        z = np.zeros(1)
+    r2 = z[:, None] ** 2 + y[None, :] ** 2
+    K = -2.0 * a.a0 * a.omega0 * np.exp(-tr * tr / a.tau ** 2) * np.cos(a.omega0 * tr)
+    sheet = K / cfg.dx[0] * np.exp(-r2 / a.waist ** 2)
+    # samples half-way beyond the last node of an open axis are outside
+    if cfg.bc[1] == OPEN and pol == 1:
+        sheet[:, ny - 1] = 0.0
+    if cfg.dims == 3 and cfg.bc[2] == OPEN and pol == 2:
+        sheet[nz - 1, :] = 0.0
+    J[pol, :, :, a.x_index] = sheet
+    return J
+
+
+def window_shift(state, injects=()):
+    """Move the window one cell along x (the window follows the laser, Sec. 2):
+    E and B shift one cell toward -x with an empty front plane, J is zeroed,
+    particles move one cell down (those leaving at x < 0 die) and each
+    species appends the particles of its entry in ``injects``: (X, u, q) in
+    window coordinates (cell units), or None."""
+    for F in (state.E, state.B):
+        F[..., :-1] = F[..., 1:].copy()
+        F[..., -1] = 0.0
+    state.J[:] = 0.0
+    target = state.species if isinstance(state, MultiState) else [state]
+    for k, sp in enumerate(target):
+        live = sp.alive > 0
+        sp.X[live, 0] -= 1.0
+        sp.alive[live & (sp.X[:, 0] < 0.0)] = 0
+        inj = injects[k] if k < len(injects) else None
+        if inj is None:
+            continue
+        Xn, un, qn = (_f64(inj[0], (-1, 3)), _f64(inj[1], (-1, 3)), _f64(inj[2]))
+        sp.X = np.concatenate([sp.X, Xn])
+        sp.u = np.concatenate([sp.u, un])
+        sp.q = np.concatenate([sp.q, qn])
+        sp.alive = np.concatenate([sp.alive, np.ones(Xn.shape[0], dtype=np.int8)])
 
 
 def divergence(cfg: Config, V):

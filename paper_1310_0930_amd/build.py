@@ -7,7 +7,8 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpic.so")
-SOURCES = ["pic_api.hip", "k_push.hip", "k_sort.hip", "k_fdtd.hip", "k_diag.hip", "k_adjoint.hip"]
+SOURCES = ["pic_api.hip", "k_push.hip", "k_sort.hip", "k_fdtd.hip", "k_diag.hip", "k_adjoint.hip",
+           "k_window.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-munsafe-fp-atomics",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

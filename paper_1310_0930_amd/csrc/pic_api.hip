@@ -186,6 +186,8 @@ int pic_create(const pic_config* cfg, pic_ctx** out) {
   ctx->sorted_cell = nullptr;
   ctx->sorted_ws = nullptr;
   ctx->sorted_np = -1;
+  ctx->antenna_on = false;
+  memset(&ctx->antenna, 0, sizeof(ctx->antenna));
   *out = ctx;
   return PIC_OK;
 }
@@ -286,9 +288,81 @@ int pic_step(pic_ctx* ctx, pic_particles* p, pic_fields* f, int32_t nsteps, void
       if ((v = pic_sort(ctx, p, ws, stream))) return v;
     }
     if ((v = pic_push_deposit(ctx, p, f, ws, stream))) return v;
+    if (ctx->antenna_on &&
+        (v = pic_antenna_add(ctx, f, &ctx->antenna, (ctx->steps_done + 0.5) * ctx->cfg.dt, stream)))
+      return v;
     if ((v = pic_field_advance(ctx, f, ws, stream))) return v;
     ctx->steps_done += 1;
   }
+  return PIC_OK;
+}
+
+static int check_antenna(const pic_ctx* ctx, const pic_antenna* a) {
+  if (!a) return PIC_EINVAL;
+  const pic_config& c = ctx->cfg;
+  if (a->polarization != 1 && a->polarization != 2) return PIC_EINVAL;
+  if (a->x_index < 0 || a->x_index >= c.n[0]) return PIC_EINVAL;
+  if (!(a->tau > 0.0) || !(a->waist > 0.0) || !isfinite(a->tau) || !isfinite(a->waist))
+    return PIC_EINVAL;
+  if (!isfinite(a->a0) || !isfinite(a->omega0) || !isfinite(a->t_center) ||
+      !isfinite(a->y_center) || !isfinite(a->z_center))
+    return PIC_EINVAL;
+  return PIC_OK;
+}
+
+int pic_antenna_add(pic_ctx* ctx, pic_fields* f, const pic_antenna* a, double t, void* stream) {
+  if (!ctx || !f || !f->J[0] || !f->J[1] || !f->J[2] || !isfinite(t)) return PIC_EINVAL;
+  int v = check_antenna(ctx, a);
+  if (v) return v;
+  if ((v = ensure_device(ctx))) return v;
+  return hip_status(launch_antenna(ctx, f, a, t, (hipStream_t)stream));
+}
+
+int pic_set_antenna(pic_ctx* ctx, const pic_antenna* a) {
+  if (!ctx) return PIC_EINVAL;
+  if (!a) {
+    ctx->antenna_on = false;
+    return PIC_OK;
+  }
+  int v = check_antenna(ctx, a);
+  if (v) return v;
+  ctx->antenna = *a;
+  ctx->antenna_on = true;
+  return PIC_OK;
+}
+
+int pic_window_shift(pic_ctx* ctx, pic_particles* p, int64_t capacity, pic_fields* f,
+                     const pic_inject* in, void* ws, void* stream) {
+  if (!ctx || !ws) return PIC_EINVAL;
+  int v = check_particles(ctx, p);
+  if (v) return v;
+  if (f && (v = check_fields(f, true))) return v;
+  const pic_config& c = ctx->cfg;
+  if (c.bc[0] != PIC_BC_OPEN) return PIC_EINVAL;  // the window moves along an open x axis
+  const int64_t n = in ? in->n : 0;
+  if (n < 0 || capacity < p->np + n || capacity >= 2147483647LL) return PIC_EINVAL;
+  if (n > 0) {
+    const int64_t ncy = c.n[1] - (c.bc[1] == PIC_BC_OPEN ? 1 : 0);
+    const int64_t ncz = c.dims == 3 ? c.n[2] - (c.bc[2] == PIC_BC_OPEN ? 1 : 0) : 1;
+    if (in->ppc < 1 || n != (int64_t)in->ppc * ncy * ncz) return PIC_EINVAL;
+    for (int d = 0; d < c.dims; ++d)
+      if (!in->off[d]) return PIC_EINVAL;
+    for (int k = 0; k < 3; ++k)
+      if (!in->u[k]) return PIC_EINVAL;
+    if ((p->q != nullptr) != (in->q != nullptr)) return PIC_EINVAL;
+    // appending needs the arrays even at np = 0
+    if (!p->cell) return PIC_EINVAL;
+    for (int d = 0; d < c.dims; ++d)
+      if (!p->off[d]) return PIC_EINVAL;
+    for (int k = 0; k < 3; ++k)
+      if (!p->u[k]) return PIC_EINVAL;
+  }
+  if ((v = ensure_device(ctx))) return v;
+  v = hip_status(launch_window_shift(ctx, p, f, in, (hipStream_t)stream));
+  if (v) return v;
+  p->np += n;
+  ctx->sorted_np = -1;  // cells moved and particles were appended: sort again
+  ctx->sorted_cell = nullptr;
   return PIC_OK;
 }
 
@@ -335,6 +409,10 @@ int pic_step_species(int32_t nspecies, pic_ctx* const* ctx, pic_particles* const
                  : pic_push_deposit_add(c, p[k], f, ws[k], stream);
       if (v) return v;
     }
+    if (ctx[0]->antenna_on &&
+        (v = pic_antenna_add(ctx[0], f, &ctx[0]->antenna,
+                             (ctx[0]->steps_done + 0.5) * ctx[0]->cfg.dt, stream)))
+      return v;
     if ((v = pic_field_advance(ctx[0], f, ws[0], stream))) return v;
     for (int32_t k = 0; k < nspecies; ++k) ctx[k]->steps_done += 1;
   }

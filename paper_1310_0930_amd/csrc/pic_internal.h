@@ -171,6 +171,8 @@ struct pic_ctx {
   int64_t sorted_np;
   int64_t sorted_cap;
   int cu_count;
+  bool antenna_on;         // pic_set_antenna: added by pic_step every step
+  pic_antenna antenna;
 };
 
 namespace pic {
@@ -187,6 +189,10 @@ int launch_push_deposit_adjoint(const pic_ctx* ctx, const pic_particles* p, cons
                                 hipStream_t s);
 int launch_deposit_rho(const pic_ctx* ctx, const pic_particles* p, double* rho, void* ws,
                        hipStream_t s, bool accumulate);
+int launch_window_shift(const pic_ctx* ctx, pic_particles* p, const pic_fields* f,
+                        const pic_inject* in, hipStream_t s);
+int launch_antenna(const pic_ctx* ctx, const pic_fields* f, const pic_antenna* a, double t,
+                   hipStream_t s);
 int launch_diagnostics(int ns, const pic_ctx* const* ctx, const pic_particles* const* p,
                        void* const* ws, const pic_fields* f, const double* rho_prev,
                        const double* gauss_ref, double* rho_out, double* gauss_out, pic_diag* out,

@@ -271,6 +271,35 @@ def _draw(w, slabs, quiet, stream, u_th, sign, q_const) -> Plasma:
     return Plasma(cell, off, u, q, q_const)
 
 
+def inject_column(w: Workload, shift: int, ions: bool = False) -> Plasma:
+    """Plasma entering the front particle column (x = n0 - 2) of a moving
+    window at its ``shift``-th move (1, 2, ...): ``ppc`` particles per cell of
+    the column, cells in storage order (y fastest, then z), drawn like the
+    initial plasma from a child seed of their own (offsets U[0,1)^D, momenta
+    N(0, u_th^2), FP32); the charge follows the density at the particle's lab
+    position x + shift (the window has moved ``shift`` cells)."""
+    pc = w.particle_cells()
+    n0, n1, _ = w.n3
+    ncol = pc[1] * (pc[2] if w.dims == 3 else 1)
+    count = ncol * w.ppc
+    rng = np.random.default_rng([w.seed, 7_000_000 + int(shift), 1 if ions else 0])
+    cy = np.arange(ncol) % pc[1]
+    cz = np.arange(ncol) // pc[1] if w.dims == 3 else np.zeros(ncol, dtype=np.int64)
+    cell = np.repeat((n0 - 2) + n0 * (cy + n1 * cz), w.ppc).astype(np.int32)
+    off = _uniform_offsets(rng, count, w.dims)
+    u = np.zeros((3, count), dtype=np.float32)
+    u_th = (w.ions.u_th if ions else w.u_th)
+    if u_th > 0.0:
+        u[:] = _round32(rng.normal(0.0, u_th, size=(3, count)))
+    sign = 1.0 if ions else -1.0
+    q_const = w.q_const_ions if ions else w.q_const
+    q = None
+    if w.ramp_cells > 0.0:
+        x_lab = (n0 - 2) + off[0].astype(np.float64) + shift
+        q = _round32(sign * np.clip(x_lab / w.ramp_cells, 0.0, 1.0) / w.ppc)
+    return Plasma(cell, off, u, q, q_const, extra={"ppc": w.ppc})
+
+
 def laser_fields(w: Workload, a0: float | None = None) -> tuple[np.ndarray, np.ndarray]:
     """Initial E, B of shape (3, n2, n1, n0), FP32-representable float64.
 

@@ -56,6 +56,17 @@ class PicDiag(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class PicInject(C.Structure):
+    _fields_ = [("n", C.c_int64), ("ppc", C.c_int32), ("off", C.c_void_p * 3),
+                ("u", C.c_void_p * 3), ("q", C.c_void_p)]
+
+
+class PicAntenna(C.Structure):
+    _fields_ = [("x_index", C.c_int32), ("polarization", C.c_int32), ("a0", C.c_double),
+                ("omega0", C.c_double), ("waist", C.c_double), ("tau", C.c_double),
+                ("t_center", C.c_double), ("y_center", C.c_double), ("z_center", C.c_double)]
+
+
 class PicError(RuntimeError):
     def __init__(self, status, what):
         super().__init__(f"{what}: {strerror(status)} ({status})")
@@ -87,6 +98,11 @@ _SIGS = {
     "pic_diagnostics_species": ([C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
                                  C.POINTER(PicFields), C.c_void_p, C.c_void_p, C.c_void_p,
                                  C.c_void_p, C.POINTER(PicDiag), C.c_void_p], C.c_int),
+    "pic_window_shift": ([C.c_void_p, C.POINTER(PicParticles), C.c_int64, C.POINTER(PicFields),
+                          C.POINTER(PicInject), C.c_void_p, C.c_void_p], C.c_int),
+    "pic_antenna_add": ([C.c_void_p, C.POINTER(PicFields), C.POINTER(PicAntenna), C.c_double,
+                         C.c_void_p], C.c_int),
+    "pic_set_antenna": ([C.c_void_p, C.POINTER(PicAntenna)], C.c_int),
     "pic_field_advance_adjoint": ([C.c_void_p, C.POINTER(PicFields), C.c_void_p, C.c_void_p],
                                   C.c_int),
     "pic_push_deposit_adjoint": ([C.c_void_p, C.POINTER(PicParticles), C.POINTER(PicFields),
@@ -225,6 +241,29 @@ def pic_diagnostics_species(ctxs, parts, wss, fields, rho_prev, gauss_ref, rho_o
     return d
 
 
+def pic_window_shift(ctx, parts: PicParticles, capacity, fields, inject, ws, stream=None):
+    _check(lib().pic_window_shift(ctx, C.byref(parts), int(capacity),
+                                  C.byref(fields) if fields is not None else None,
+                                  C.byref(inject) if inject is not None else None,
+                                  C.c_void_p(ws), _stream(stream)), "pic_window_shift")
+
+
+def pic_antenna_add(ctx, fields: PicFields, antenna: PicAntenna, t, stream=None):
+    _check(lib().pic_antenna_add(ctx, C.byref(fields), C.byref(antenna), float(t), _stream(stream)),
+           "pic_antenna_add")
+
+
+def pic_set_antenna(ctx, antenna):
+    _check(lib().pic_set_antenna(ctx, C.byref(antenna) if antenna is not None else None),
+           "pic_set_antenna")
+
+
+def antenna_struct(x_index, polarization, a0, omega0, waist, tau, t_center, y_center,
+                   z_center=0.0) -> PicAntenna:
+    return PicAntenna(int(x_index), int(polarization), float(a0), float(omega0), float(waist),
+                      float(tau), float(t_center), float(y_center), float(z_center))
+
+
 def pic_field_advance_adjoint(ctx, lam_fields: PicFields, ws, stream=None):
     _check(lib().pic_field_advance_adjoint(ctx, C.byref(lam_fields), C.c_void_p(ws), _stream(stream)),
            "pic_field_advance_adjoint")
@@ -297,7 +336,7 @@ class Simulation:
         self.species = []  # further species sharing these fields (add_species)
         self.q_over_m = q_over_m
 
-    def add_species(self, plasma, q_over_m, q_const, with_id=True):
+    def add_species(self, plasma, q_over_m, q_const, with_id=True, capacity=None):
         """Another species on this grid (mobile ions): its own context (q/m,
         uniform charge), particle arrays and workspace, pushed in and
         depositing into this simulation's E, B, J.  Returns its Simulation."""
@@ -306,7 +345,7 @@ class Simulation:
                         c.sort_every, q_over_m, q_const, self.device)
         sp.E, sp.B, sp.J = self.E, self.B, self.J
         sp._fields = self._fields
-        sp._load_particles(plasma, with_id)
+        sp._load_particles(plasma, with_id, capacity)
         self.species.append(sp)
         return sp
 
@@ -324,8 +363,10 @@ class Simulation:
             pass
 
     # ---- state upload / download
-    def load(self, plasma, E=None, B=None, with_id=True):
-        """Upload a Plasma (inputs.Plasma) and initial fields (3, n2, n1, n0)."""
+    def load(self, plasma, E=None, B=None, with_id=True, capacity=None):
+        """Upload a Plasma (inputs.Plasma) and initial fields (3, n2, n1, n0).
+        ``capacity`` (>= plasma.np) sizes the particle arrays for a moving
+        window that appends particles."""
         torch = self.torch
         dev = self.device
         if E is not None:
@@ -333,18 +374,30 @@ class Simulation:
         if B is not None:
             self.B.copy_(torch.from_numpy(np.asarray(B).reshape(3, -1)).to(dev, self.real))
         self.J.zero_()
-        return self._load_particles(plasma, with_id)
+        return self._load_particles(plasma, with_id, capacity)
 
-    def _load_particles(self, plasma, with_id):
+    def _load_particles(self, plasma, with_id, capacity=None):
         torch = self.torch
         dev = self.device
         self.np = plasma.np
-        self.cell = torch.from_numpy(np.ascontiguousarray(plasma.cell)).to(dev)
-        self.off = torch.from_numpy(np.ascontiguousarray(plasma.off)).to(dev, self.real).contiguous()
-        self.u = torch.from_numpy(np.ascontiguousarray(plasma.u)).to(dev, self.real).contiguous()
-        self.q = None if plasma.q is None else torch.from_numpy(plasma.q).to(dev, self.real)
-        self.id = torch.arange(self.np, dtype=torch.int32, device=dev) if with_id else None
-        nbytes = pic_workspace_bytes(self.ctx, self.np)
+        cap = self.np if capacity is None else int(capacity)
+        if cap < self.np:
+            raise ValueError("capacity below the particle count")
+        self.capacity = cap
+
+        def put(a, dtype):
+            t = torch.zeros(a.shape[:-1] + (cap,), dtype=dtype, device=dev)
+            t[..., : self.np] = torch.from_numpy(np.ascontiguousarray(a)).to(dev, dtype)
+            return t
+
+        self.cell = put(plasma.cell, torch.int32)
+        self.off = put(plasma.off, self.real)
+        self.u = put(plasma.u, self.real)
+        self.q = None if plasma.q is None else put(plasma.q, self.real)
+        self.id = None
+        if with_id:
+            self.id = torch.arange(cap, dtype=torch.int32, device=dev)
+        nbytes = pic_workspace_bytes(self.ctx, cap)
         self.ws = torch.zeros(nbytes, dtype=torch.uint8, device=dev)
         self._parts = PicParticles(
             self.np, self.cell.data_ptr(),
@@ -357,11 +410,12 @@ class Simulation:
     def download(self):
         """Host copies: cell, off (3,np), u (3,np), id, E, B, J (3, n2, n1, n0), float64."""
         shp = (3, self.n[2], self.n[1], self.n[0])
+        n = self.np
         out = {
-            "cell": self.cell.cpu().numpy(),
-            "off": self.off.double().cpu().numpy(),
-            "u": self.u.double().cpu().numpy(),
-            "id": None if self.id is None else self.id.cpu().numpy(),
+            "cell": self.cell[:n].cpu().numpy(),
+            "off": self.off[:, :n].double().cpu().numpy(),
+            "u": self.u[:, :n].double().cpu().numpy(),
+            "id": None if self.id is None else self.id[:n].cpu().numpy(),
             "E": self.E.double().cpu().numpy().reshape(shp),
             "B": self.B.double().cpu().numpy().reshape(shp),
             "J": self.J.double().cpu().numpy().reshape(shp),
@@ -429,6 +483,40 @@ class Simulation:
         out = d.as_dict()
         out["gauss_field"] = g
         return Diag(out, rho)
+
+    # ---- moving window and antenna
+    def window_shift(self, inject=None, species_inject=()):
+        """Move the window one cell along x: fields shift, particles move one
+        cell down (leaving ones absorbed), and ``inject`` (an inputs.Plasma of
+        the front column, or None) is appended; ``species_inject`` gives the
+        front-column particles of each further species."""
+        pic_window_shift(self.ctx, self._parts, self.capacity, self._fields,
+                         self._inject_struct(inject), self.ws.data_ptr(), self.stream)
+        self.np = self._parts.np
+        for k, sp in enumerate(self.species):
+            inj = species_inject[k] if k < len(species_inject) else None
+            pic_window_shift(sp.ctx, sp._parts, sp.capacity, None, sp._inject_struct(inj),
+                             sp.ws.data_ptr(), self.stream)
+            sp.np = sp._parts.np
+
+    def _inject_struct(self, plasma):
+        if plasma is None or plasma.np == 0:
+            return None
+        torch = self.torch
+        off = torch.from_numpy(np.ascontiguousarray(plasma.off)).to(self.device, self.real)
+        u = torch.from_numpy(np.ascontiguousarray(plasma.u)).to(self.device, self.real)
+        q = None if plasma.q is None else torch.from_numpy(plasma.q).to(self.device, self.real)
+        self._inj_keep = (off, u, q)  # alive until the stream has consumed them
+        ppc = plasma.extra.get("ppc", 1)
+        return PicInject(plasma.np, int(ppc), (C.c_void_p * 3)(*[off[d].data_ptr() for d in range(3)]),
+                         (C.c_void_p * 3)(*[u[c].data_ptr() for c in range(3)]),
+                         q.data_ptr() if q is not None else None)
+
+    def set_antenna(self, antenna):
+        pic_set_antenna(self.ctx, antenna)
+
+    def antenna_add(self, antenna, t):
+        pic_antenna_add(self.ctx, self._fields, antenna, t, self.stream)
 
     def read_flags(self, clear=False):
         return pic_read_flags(self.ctx, self.ws.data_ptr(), clear, self.stream)

@@ -13,6 +13,7 @@ import pytest
 from scipy.interpolate import BSpline
 
 import oracle as O
+from oracle import OPEN as OPEN_
 from paper_1310_0930_amd import inputs as I
 
 RNG = np.random.default_rng(20131003)
@@ -633,3 +634,110 @@ def test_two_species_continuity_and_gauss(dims):
     g = O.divergence(c, s.E) - s.rho() - g0
     assert np.abs(g[mask]).max() < 1e-11 * np.abs(s.rho()).max() + 1e-13
 
+
+
+# ---------------------------------------------------------------- moving window, antenna
+def test_discrete_poynting_identity_with_antenna():
+    """With B kept at integer times by two half steps, W~ = 1/2 (|E|^2 + |B|^2)
+    - dt^2/8 |C E|^2 (times dV) changes over a step by exactly
+    -dt/2 <J^{n+1/2}, E^n + E^{n+1}> dV (periodic grid): the antenna's current
+    enters the E update with the right sign and scale."""
+    c = cfg2(n=(40, 24), dx=(0.1, 0.2), order=2)
+    a = O.Antenna(x_index=10, polarization=1, a0=0.7, omega0=5.0, waist=1.5, tau=0.6,
+                  t_center=1.0, y_center=2.4)
+    E = 0.01 * RNG.normal(size=(3,) + c.shape)
+    B = 0.01 * RNG.normal(size=(3,) + c.shape)
+    s = O.State(c, np.zeros((0, 3)), np.zeros((0, 3)), np.zeros(0), E, B)
+    s.antenna = a
+    dV = c.dx[0] * c.dx[1]
+
+    def wt(st):
+        ce = O.curl_e(c, st.E)
+        return 0.5 * dV * (np.sum(st.E ** 2) + np.sum(st.B ** 2)) - c.dt ** 2 / 8 * dV * np.sum(ce ** 2)
+
+    for _ in range(30):
+        E0, w0 = s.E.copy(), wt(s)
+        s.step(1)
+        work = -0.5 * c.dt * dV * np.sum(s.J * (E0 + s.E))
+        assert abs(wt(s) - w0 - work) < 1e-12 * (abs(w0) + abs(work) + 1e-30)
+    assert np.abs(s.J).max() > 0
+
+
+def test_antenna_emits_the_requested_field():
+    """A uniform current sheet (quasi-1D: periodic y, huge waist) at small
+    k dx radiates a0 omega0 env(t - r) cos(omega0 (t - r - t_c)) on both sides
+    (a sheet current K gives E = -K/2): the field seen 30 cells from the
+    antenna peaks at a0 omega0 within 1 %."""
+    n0 = 400
+    c = O.Config(2, (n0, 4, 1), (0.05, 0.2, 1.0), 0.5 * 0.05, 2, (OPEN_, 0, 0))
+    a = O.Antenna(x_index=200, polarization=1, a0=0.3, omega0=2.0, waist=1e9, tau=2.0,
+                  t_center=6.0, y_center=0.0)
+    s = O.State(c, np.zeros((0, 3)), np.zeros((0, 3)), np.zeros(0), c.zeros_field(),
+                c.zeros_field())
+    s.antenna = a
+    probe = 230
+    trace = []
+    for _ in range(int(14.0 / c.dt)):
+        s.step(1)
+        trace.append(s.E[1, 0, 0, probe])
+    peak = np.max(np.abs(trace))
+    assert abs(peak / (a.a0 * a.omega0) - 1.0) < 1e-2
+
+
+@pytest.mark.parametrize("dims", [2, 3])
+def test_window_shift_moves_fields_and_particles_together(dims):
+    """After one window shift the Gauss residual D.E - rho at node i equals
+    its value at node i+1 before (fields and particles moved by exactly one
+    cell), and every surviving particle moved by exactly -1 in x."""
+    if dims == 2:
+        w = I.Workload("t", 2, (24, 12), (0.1, 0.2), 2, 4, 0.2, 1, bc=(1, 0), seed=21)
+    else:
+        w = I.Workload("t", 3, (16, 8, 6), (0.1, 0.2, 0.2), 3, 2, 0.2, 1, bc=(1, 0, 0), seed=22)
+    c, s = _thermal_state(w)
+    s.E += 0.01 * RNG.normal(size=s.E.shape)
+    s.step(2)
+    g0 = O.divergence(c, s.E) - s.rho()
+    X0, alive0 = s.X.copy(), s.alive.copy()
+    O.window_shift(s)
+    g1 = O.divergence(c, s.E) - s.rho()
+    # away from the faces (absorbed particles at the back still reached
+    # order/2 + 1 node planes; the front plane of E is new)
+    m = 2 + w.order // 2
+    np.testing.assert_allclose(g1[..., m:-m], g0[..., m + 1:-m + 1], atol=1e-13)
+    keep = (alive0 > 0) & (X0[:, 0] >= 1.0)
+    np.testing.assert_array_equal(s.X[keep, 0], X0[keep, 0] - 1.0)
+    assert np.all(s.alive[(alive0 > 0) & (X0[:, 0] < 1.0)] == 0)
+
+
+def test_window_keeps_a_pulse_at_the_yee_group_velocity():
+    """A quasi-1D laser pulse in vacuum with the window moving one cell per
+    dx of light travel: in the lab frame (window position + shifts) the
+    pulse centroid moves at the Yee group velocity v_g = cos(k dx/2) /
+    cos(omega dt/2) (sin(omega dt/2)/dt = sin(k dx/2)/dx), within 2e-3."""
+    n0, dx = 300, 0.1
+    lz = I.Laser(a0=0.1, omega0=10.0, waist=1e9, tau=1.5, x_center=15.0)
+    w = I.Workload("t", 2, (n0, 4), (dx, 0.2), 2, 1, 0.0, 1, bc=(1, 0), laser=lz)
+    E, B = I.laser_fields(w)
+    c = O.Config(2, w.n3, w.dx3, w.dt, 2, w.bc3)
+    s = O.State(c, np.zeros((0, 3)), np.zeros((0, 3)), np.zeros(0), E, B)
+    x = np.arange(n0) * dx
+
+    def centroid():
+        e2 = s.E[1, 0, 0] ** 2
+        return np.sum(x * e2) / np.sum(e2)
+
+    shifts, ts, cs = 0, [], []
+    steps = int(8.0 / c.dt)
+    for n in range(1, steps + 1):
+        s.step(1)
+        while (shifts + 1) * dx <= n * c.dt:  # the window follows light
+            O.window_shift(s)
+            shifts += 1
+        ts.append(n * c.dt)
+        cs.append(centroid() + shifts * dx)
+    vg = np.polyfit(ts[len(ts) // 4:], cs[len(cs) // 4:], 1)[0]
+    k = lz.omega0
+    om = 2 / c.dt * np.arcsin(c.dt / dx * np.sin(k * dx / 2))
+    vg_yee = np.cos(k * dx / 2) / np.cos(om * c.dt / 2)
+    assert abs(vg - vg_yee) < 2e-3
+    assert abs(vg_yee - 1.0) > 1e-2  # the check can tell v_g from c
