@@ -120,6 +120,53 @@ def run_gpu(w, real_bytes, steps, warmup, log):
     }
 
 
+def run_window(w, real_bytes, shifts, log):
+    """Moving-window shift on workload w's grid (x made open): ms per shift
+    and HBM rate against the algorithmic bytes (E, B read and written, J
+    zeroed, cells read and written, the front column's particles read and
+    written).  The injected columns are uploaded before the timed region."""
+    import ctypes as C
+    import torch
+    from paper_1310_0930_amd import pic as P
+    wo = w.with_(bc=(I.OPEN,) + tuple(w.bc3[1:w.dims]))
+    pl = I.make_plasma(wo)
+    E, B = I.laser_fields(wo)
+    pc = wo.particle_cells()
+    ncol = pc[1] * (pc[2] if wo.dims == 3 else 1) * wo.ppc
+    sim = P.Simulation.from_workload(wo, real_bytes=real_bytes)
+    sim.load(pl, E, B, with_id=False, capacity=pl.np + (shifts + 2) * ncol)
+    del pl
+    keep, injs = [], []
+    for k in range(shifts + 1):
+        col = I.inject_column(wo, k + 1)
+        off = torch.from_numpy(col.off).to(sim.device, sim.real)
+        u = torch.from_numpy(col.u).to(sim.device, sim.real)
+        q = None if col.q is None else torch.from_numpy(col.q).to(sim.device, sim.real)
+        keep.append((off, u, q))
+        injs.append(P.PicInject(col.np, wo.ppc, (C.c_void_p * 3)(*[off[d].data_ptr() for d in range(3)]),
+                                (C.c_void_p * 3)(*[u[c].data_ptr() for c in range(3)]),
+                                q.data_ptr() if q is not None else None))
+    P.pic_window_shift(sim.ctx, sim._parts, sim.capacity, sim._fields, injs[0], sim.ws.data_ptr())
+    torch.cuda.synchronize()
+    np0 = sim._parts.np
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for k in range(1, shifts + 1):
+        P.pic_window_shift(sim.ctx, sim._parts, sim.capacity, sim._fields, injs[k], sim.ws.data_ptr())
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / shifts
+    np_mean = np0 + ncol * (shifts + 1) / 2
+    R = real_bytes
+    per_inject = 2 * R * (wo.dims + 3) + 4 + (2 * R if wo.ramp_cells > 0 else 0)
+    alg = wo.ncell * R * (6 * 2 + 3) + 8 * np_mean + ncol * per_inject
+    log(f"window shift {wo.name} real={R}: {ms:.4f} ms per shift, {alg / ms / 1e6:.1f} GB/s")
+    return {"ms_per_shift": round(ms, 5), "alg_bytes_per_shift": int(alg),
+            "roofline": {"bound": "hbm", "achieved": round(alg / ms / 1e6, 2), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(alg / ms / 1e6 / HBM_PEAK_GBS, 4)},
+            "shifts_per_step": round(wo.dt / wo.dx3[0], 4)}
+
+
 def cpu_baseline(w, log, budget_s=12.0):
     """The FP64 oracle (as it stands) on the host cores: one push/deposit pass
     over a bounded prefix of the workload's particles plus one full-grid FDTD
@@ -166,6 +213,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quiet", action="store_true")
+    ap.add_argument("--window", type=int, default=0, metavar="K",
+                    help="also time K moving-window shifts on the workload's grid (x made open)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 1 GiB device-to-device copy (for scaling the "
                          "rocprofv3 FETCH_SIZE/WRITE_SIZE counters)")
@@ -223,6 +272,10 @@ def main():
                        "ms_per_step": round(r64["ms_per_step"], 5),
                        "push_deposit_pushes_per_s": r64["np"] / (r64["push_ms_mean"] * 1e-3),
                        "roofline": roof(r64, 8, "f64"), "device_flags": r64["flags"]}
+    if a.window > 0:
+        out["window_shift"] = {"f32": run_window(w, 4, a.window, log)}
+        if not a.no_fp64:
+            out["window_shift"]["f64"] = run_window(w, 8, a.window, log)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, log)
     t3 = json.load(open(os.path.join(ROOT, "tests", "golden", "paper_table3.json")))
