@@ -168,8 +168,19 @@ __global__ void k_sort_scatter(SortArrays<R> A, long np, int ncell, int dims,
                                const int* __restrict__ keys, int* __restrict__ cursor,
                                DevFlags* flg) {
   const long p = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  const int cl = p < np ? A.cell[p] : 0;
-  const int key = p < np ? keys[p] : -1;
+  const bool in = p < np;
+  // the payload is loaded first, so that its latency overlaps the cursor
+  // atomic's round trip
+  const int cl = in ? A.cell[p] : 0;
+  const int key = in ? keys[p] : -1;
+  R o[3] = {R(0), R(0), R(0)}, u[3] = {R(0), R(0), R(0)}, qv = R(0);
+  int idv = 0;
+  if (in) {
+    for (int d = 0; d < dims; ++d) o[d] = A.off[d][p];
+    for (int c = 0; c < 3; ++c) u[c] = A.u[c][p];
+    if (A.q) qv = A.q[p];
+    if (A.id) idv = A.id[p];
+  }
   int head, len;
   wave_runs(key, head, len);
   const int lane = threadIdx.x & 63;
@@ -180,22 +191,22 @@ __global__ void k_sort_scatter(SortArrays<R> A, long np, int ncell, int dims,
     // largest |q| as a float bit pattern (non-negative floats order as
     // unsigned integers), rounded up so that it bounds every |q| of type R
     unsigned m = 0u;
-    if (p < np) {
-      const R qa = fabs(A.q[p]);
+    if (in) {
+      const R qa = fabs(qv);
       float f = (float)qa;
       if ((R)f < qa) f = nextafterf(f, INFINITY);
       m = __float_as_uint(f);
     }
-    for (int o = 32; o > 0; o >>= 1) m = max(m, (unsigned)__shfl_xor((int)m, o, 64));
+    for (int sh = 32; sh > 0; sh >>= 1) m = max(m, (unsigned)__shfl_xor((int)m, sh, 64));
     if (lane == 0) atomicMax(&flg->qmax, m);
   }
-  if (p >= np) return;
+  if (!in) return;
   const long dst = (long)base + (lane - head);
   A.t_cell[dst] = (cl >= 0 && cl < ncell) ? cl : -1;
-  for (int d = 0; d < dims; ++d) A.t_off[d][dst] = A.off[d][p];
-  for (int c = 0; c < 3; ++c) A.t_u[c][dst] = A.u[c][p];
-  if (A.id) A.t_id[dst] = A.id[p];
-  if (A.q) A.t_q[dst] = A.q[p];
+  for (int d = 0; d < dims; ++d) A.t_off[d][dst] = o[d];
+  for (int c = 0; c < 3; ++c) A.t_u[c][dst] = u[c];
+  if (A.id) A.t_id[dst] = idv;
+  if (A.q) A.t_q[dst] = qv;
 }
 
 template <typename R>
