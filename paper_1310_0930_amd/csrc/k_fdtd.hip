@@ -56,6 +56,20 @@ __device__ __forceinline__ int nb(const FdParams& P, int i, int j, int k, int d,
   return L[0] + P.n[0] * (L[1] + P.n[1] * L[2]);
 }
 
+// Block index with the 8 XCDs each taking a contiguous range of blocks
+// (consecutive block ids are dealt round-robin to the XCDs): the neighbour
+// rows and planes a stencil reads then sit in the same XCD's L2.  The grid
+// must be a multiple of 8 blocks; the mapping is a permutation of it.
+__device__ __forceinline__ int xcd_block() {
+  const int per = gridDim.x >> 3;
+  return (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+}
+
+__host__ inline unsigned xcd_grid(long ncell) {
+  const long g = (ncell + 255) / 256;
+  return (unsigned)((g + 7) / 8 * 8);
+}
+
 template <typename R>
 __device__ __forceinline__ R ld_or0(const R* a, int idx) {
   return idx < 0 ? R(0) : a[idx];
@@ -66,7 +80,7 @@ template <typename R>
 __global__ void k_half_b(FdParams P, const R* __restrict__ E0, const R* __restrict__ E1,
                          const R* __restrict__ E2, R* __restrict__ B0, R* __restrict__ B1,
                          R* __restrict__ B2, R hx, R hy, R hz, int ncell) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int idx = xcd_block() * blockDim.x + threadIdx.x;
   if (idx >= ncell) return;
   int i, j, k;
   decompose(P, idx, i, j, k);
@@ -115,7 +129,7 @@ __global__ void k_advance_e(FdParams P, MurPlanes M, R* __restrict__ E0, R* __re
                             const R* __restrict__ B2, const R* __restrict__ J0,
                             const R* __restrict__ J1, const R* __restrict__ J2, R gx, R gy, R gz,
                             R dt, int ncell, R* __restrict__ save) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int idx = xcd_block() * blockDim.x + threadIdx.x;
   if (idx >= ncell) return;
   int i, j, k;
   decompose(P, idx, i, j, k);
@@ -227,7 +241,7 @@ static int launch_fa(const pic_ctx* ctx, const pic_fields* f, void* ws, hipStrea
         if (P.open[d] && c != d) off += (long)P.n[a] * P.n[b];
       }
   }
-  const unsigned grid = (unsigned)((ncell + 255) / 256);
+  const unsigned grid = xcd_grid(ncell);  // a multiple of 8 blocks (xcd_block)
   k_half_b<R><<<dim3(grid), dim3(256), 0, s>>>(P, E[0], E[1], E[2], B[0], B[1], B[2], h[0], h[1],
                                               h[2], ncell);
   k_advance_e<R><<<dim3(grid), dim3(256), 0, s>>>(P, M, E[0], E[1], E[2], B[0], B[1], B[2], J[0],
