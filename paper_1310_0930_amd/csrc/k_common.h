@@ -17,6 +17,8 @@ __device__ __forceinline__ int wrap1(int i, int n) {
 __device__ __forceinline__ int axis_slot(int i, int n, int open, int st) {
   if (!open) {
     if (i >= 0 && i < n) return i;
+    if (i < 0 && i >= -n) return i + n;
+    if (i >= n && i < 2 * n) return i - n;
     const int m = i % n;
     return m < 0 ? m + n : m;
   }
@@ -34,6 +36,12 @@ __device__ __forceinline__ void axis_slots(int i, int n, int open, int stride, i
   }
   s[0] = (i < 0 || i > n - 1) ? -1 : i * stride;
   s[1] = (i < 0 || i > n - 2) ? -1 : i * stride;
+}
+
+// True when the samples lo .. lo+w-1 of an axis need no wrap and no open
+// boundary handling for either staggering (a region's fast path).
+__device__ __forceinline__ bool axis_inside(int lo, int w, int n, int open) {
+  return lo >= 0 && lo + w <= n - open;
 }
 
 template <typename R>

@@ -194,13 +194,15 @@ struct LdsCurrent {
   __device__ __forceinline__ void put(int comp, int i, int j, int k, C f, C a) const {
     double* t = &seg[comp * G::j_vol + (k * G::jx + j) * G::jx + i];
     if constexpr (G::fixed) {
-      // |f a| < 2^51: adding 1.5 * 2^52 rounds the product to an integer
-      // held in the low mantissa bits (one rounding, fused), and
-      // subtracting the constant's bit pattern leaves that integer in two's
-      // complement (the constant's low word is zero)
+      // |f a| < 2^51: adding 1.5 * 2^52 rounds the product to an integer n
+      // held in the low mantissa bits (one rounding, fused); the bit pattern
+      // is then 0x4338 << 48 plus n in two's complement.  The tile adds the
+      // patterns as 64-bit integers: the constant parts only touch bits
+      // 48..63, so bits 0..47 hold the sum of the n modulo 2^48, which is
+      // the exact sum as long as it stays below 2^47 in magnitude (the
+      // scales guarantee it; the flush sign-extends bit 47).
       const double y = fma(f, a, 6755399441055744.0);
-      atomicAdd((unsigned long long*)t,
-                (unsigned long long)(__double_as_longlong(y) - 0x4338000000000000LL));
+      atomicAdd((unsigned long long*)t, (unsigned long long)__double_as_longlong(y));
     } else {
       atomicAdd(t, (double)(f * a));
     }

@@ -40,45 +40,90 @@ struct SegQueue {
   static constexpr int LEN = on ? NW * CAP : 1;
 };
 
-// Tile kernel: one workgroup per tile; particles within the drift allowance
-// of the tile run out of LDS.  Any other particle (drifted further, or moving
-// half a cell or more in one step) is left untouched and appended to the
-// deferred list for k_push_deferred.
-template <int DIMS, int ORDER, typename R>
-__global__ void __launch_bounds__((Geo<DIMS, ORDER, R>::NT)) k_push_tile(
-    KParams<R> P, DParts<R> pa, DFields<R> F, const int* __restrict__ starts,
-    int* __restrict__ deferred, DevFlags* flg) {
-  using G = Geo<DIMS, ORDER, R>;
-  using Q = SegQueue<DIMS, ORDER, R>;
-  __shared__ R s_eb[6 * G::e_vol];
-  __shared__ double s_j[3 * G::j_vol];
-  __shared__ int q_idx[Q::LEN];
-  __shared__ R q_val[Q::NV][Q::LEN];
+// Tiles for persistent workgroups.  Tiles are split into 8 contiguous
+// ranges, one per XCD: a workgroup takes tiles from its own XCD's range
+// first (neighbouring tiles share halo samples in that XCD's L2; dispatch
+// places workgroup b on XCD b mod 8) and then from the other ranges in
+// turn; `xk` counts the ranges it has found used up.  A claim is one atomic
+// increment of a range counter, issued early so that its latency overlaps
+// other work, and resolved later (one thread does both).
+__device__ inline unsigned claim_issue(DevFlags* flg, int xk) {
+  return xk < 8 ? atomicAdd(&flg->tile_next[(blockIdx.x + xk) & 7], 1u) : 0u;
+}
 
-  // XCD-aware remap: consecutive block ids go round-robin over the 8 XCDs,
-  // so give each XCD a contiguous range of tiles (neighbouring tiles share
-  // halo samples in that XCD's L2).
-  const int tile = (blockIdx.x & 7) * P.per_xcd + (blockIdx.x >> 3);
-  if (tile >= P.ntiles) return;
-  const int pbeg = starts[tile], pend = starts[tile + 1];
-  if (pbeg == pend) return;
-  const int tx = tile % P.ntile[0];
-  const int ty = (tile / P.ntile[0]) % P.ntile[1];
-  const int tz = tile / (P.ntile[0] * P.ntile[1]);
-  const int org[3] = {tx * G::T, ty * G::T, tz * G::TZ};
+// Resolves a claim to a non-empty tile (claiming again past empty tiles and
+// used-up ranges); returns -1 once every range is used up.
+__device__ inline int claim_resolve(unsigned local, const int* __restrict__ starts, DevFlags* flg,
+                                    int per_xcd, int ntiles, int& xk, int& beg, int& end) {
+  while (xk < 8) {
+    const int t = (int)((blockIdx.x + xk) & 7) * per_xcd + (int)local;
+    if (local >= (unsigned)per_xcd || t >= ntiles) {
+      ++xk;
+    } else {
+      beg = starts[t];
+      end = starts[t + 1];
+      if (beg != end) return t;
+    }
+    local = claim_issue(flg, xk);
+  }
+  return -1;
+}
+
+// The low 48 bits of a fixed-point tile sum, sign-extended (the sum itself).
+__device__ __forceinline__ long long sext48(long long x) {
+  return (long long)((unsigned long long)x << 16) >> 16;
+}
+
+// Next batch of 64 particles of the current tile for this wavefront.
+__device__ __forceinline__ int take_batch(int* ctr) {
+  int b = 0;
+  if ((threadIdx.x & 63) == 0) b = atomicAdd(ctr, 1);
+  return __builtin_amdgcn_readfirstlane(b);
+}
+
+// threadIdx.x behind an opaque copy: index arithmetic on it inside the
+// persistent tile loop stays there instead of being hoisted out of the loop
+// and held in registers across the particle loop.
+__device__ __forceinline__ int opaque_tid() {
+  int t = (int)threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t;
+}
+
+// E and B of a tile + halo (zero outside open faces) into registers.  Each
+// thread takes region samples and loads the six components there, with the
+// storage offsets along each axis formed once per sample; all loads are in
+// flight together.
+template <int DIMS, int ORDER, typename R, int NR>
+__device__ inline void stage_load(const KParams<R>& P, const DFields<R>& F, const int org[3],
+                                  R (&stage)[NR][6]) {
+  using G = Geo<DIMS, ORDER, R>;
   const int open0 = P.bc[0] == PIC_BC_OPEN, open1 = P.bc[1] == PIC_BC_OPEN;
   const int open2 = DIMS == 3 && P.bc[2] == PIC_BC_OPEN;
-
-  // stage E and B of tile + halo (zero outside open faces).  Each thread
-  // takes region samples and loads the six components there, with the
-  // storage offsets along each axis formed once per sample; every load is
-  // issued before the first LDS store so that their latencies overlap.
-  constexpr int NR = (G::e_vol + G::NT - 1) / G::NT;
   const int str1 = P.n[0], str2 = P.n[0] * P.n[1];
-  R stage[NR][6];
+  const int tid = opaque_tid();
+  const int bx = org[0] + G::e_lo, by = org[1] + G::e_lo, bz = org[2] + G::e_lo_z;
+  if (axis_inside(bx, G::ex, P.n[0], open0) && axis_inside(by, G::ex, P.n[1], open1) &&
+      (DIMS == 2 || axis_inside(bz, G::ez, P.n[2], open2))) {
+    // no wrap, no boundary: one storage offset per sample for all components
+    const int base = (DIMS == 3 ? bz * str2 : 0) + by * str1 + bx;
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+      const int r = tid + k * G::NT;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) stage[k][c] = R(0);
+      if (r < G::e_vol) {
+        const int lx = r % G::ex, ly = (r / G::ex) % G::ex, lz = r / (G::ex * G::ex);
+        const int o = base + (DIMS == 3 ? lz * str2 : 0) + ly * str1 + lx;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) stage[k][c] = (c >= 3 ? F.B[c - 3] : F.E[c])[o];
+      }
+    }
+    return;
+  }
 #pragma unroll
   for (int k = 0; k < NR; ++k) {
-    const int r = threadIdx.x + k * G::NT;
+    const int r = tid + k * G::NT;
 #pragma unroll
     for (int c = 0; c < 6; ++c) stage[k][c] = R(0);
     if (r < G::e_vol) {
@@ -98,191 +143,316 @@ __global__ void __launch_bounds__((Geo<DIMS, ORDER, R>::NT)) k_push_tile(
       }
     }
   }
-#pragma unroll
-  for (int k = 0; k < NR; ++k) {
-    const int r = threadIdx.x + k * G::NT;
-    if (r < G::e_vol) {
-#pragma unroll
-      for (int c = 0; c < 6; ++c) s_eb[c * G::e_vol + r] = stage[k][c];
-    }
-  }
-  for (int idx = threadIdx.x; idx < 3 * G::j_vol; idx += G::NT) s_j[idx] = 0.0;
+}
 
-  // Scales of the fixed-point current tile (single form).  A contribution
-  // to J_c is q jfac_c P A with |P| <= |move along c| < 1/2 and 0 <= A <= 1
-  // (P is a difference of the cumulative shape, A an average of products
-  // of weights), so |contribution| < qmax |jfac_c| / 2; in 2D J_z is
-  // q v_z f A with |v_z| < 1, f <= 1, so qmax bounds it.  A tile sample
-  // receives at most (DIMS+1) contributions per particle of the tile.  The
-  // power-of-two scale 2^K keeps every scaled contribution below 2^50 and
-  // every sum below 2^62, so contributions round to integers at ~2^-48 of
-  // the bound (single-precision values are kept exactly) and the 64-bit
-  // tile sums are exact.  A particle whose |q| exceeds the bound the sort
-  // recorded (charges changed since) takes the global-memory path.
-  R jf[3] = {P.jfac[0], P.jfac[1], P.jfac[2]};
-  R zs = R(1);
-  int Ks[3] = {0, 0, 0};
-  const float qmax = pa.q ? __uint_as_float(flg->qmax) : fabsf((float)P.q_const);
-  const bool qmax_ok = qmax <= 3.0e38f;
-  if constexpr (G::fixed) {
-    const unsigned ncontrib = (unsigned)(DIMS + 1) * (unsigned)(pend - pbeg);
-    const int g = 32 - __clz((int)(ncontrib - 1u));  // ncontrib <= 2^g
-    const int top = g > 12 ? 62 - g : 50;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const bool z2 = DIMS == 2 && c == 2;
-      int e = 0;
-      frexpf(z2 ? qmax : qmax * fabsf((float)P.jfac[c]) * 0.5f, &e);  // bound < 2^e
-      // uniform over the workgroup: keep the scales in scalar registers
-      Ks[c] = __builtin_amdgcn_readfirstlane(qmax_ok ? top - e : 0);
-      const float sc = ldexpf(z2 ? 1.0f : (float)P.jfac[c], Ks[c]);
-      const float su = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(sc)));
-      if (z2)
-        zs = su;
-      else
-        jf[c] = su;
-    }
+template <int DIMS, int ORDER, typename R>
+__device__ inline void tile_origin(const KParams<R>& P, int tile, int org[3]) {
+  using G = Geo<DIMS, ORDER, R>;
+  org[0] = (tile % P.ntile[0]) * G::T;
+  org[1] = ((tile / P.ntile[0]) % P.ntile[1]) * G::T;
+  org[2] = (tile / (P.ntile[0] * P.ntile[1])) * G::TZ;
+}
+
+// Tile kernel: persistent workgroups, each taking tiles until none is left;
+// particles within the drift allowance of the tile run out of LDS.  Any
+// other particle (drifted further, or moving half a cell or more in one
+// step) is left untouched and appended to the deferred list for
+// k_push_deferred.  The tiles of one workgroup are software-pipelined: a
+// wavefront that has finished its particles issues the loads of the next
+// tile's fields (into registers) while the other wavefronts finish, and
+// the flush of the current tile's current runs while they are in flight.
+template <int DIMS, int ORDER, typename R>
+__global__ void __launch_bounds__((Geo<DIMS, ORDER, R>::NT)) k_push_tile(
+    KParams<R> P, DParts<R> pa, DFields<R> F, const int* __restrict__ starts,
+    int* __restrict__ deferred, DevFlags* flg) {
+  using G = Geo<DIMS, ORDER, R>;
+  using Q = SegQueue<DIMS, ORDER, R>;
+  __shared__ R s_eb[6 * G::e_vol];
+  __shared__ double s_j[3 * G::j_vol];
+  __shared__ int q_idx[Q::LEN];
+  __shared__ R q_val[Q::NV][Q::LEN];
+  // Tile ids two deep: while tile i runs, slot (i+1)&1 holds tile i+1
+  // (tile id, first and end particle) and thread 0 resolves tile i+2 into
+  // slot i&1, which nobody reads until the next tile.
+  __shared__ int s_q[2][3];
+  __shared__ int s_batch;  // next batch of the current tile
+
+  const int open0 = P.bc[0] == PIC_BC_OPEN, open1 = P.bc[1] == PIC_BC_OPEN;
+  const int open2 = DIMS == 3 && P.bc[2] == PIC_BC_OPEN;
+  const int str1 = P.n[0], str2 = P.n[0] * P.n[1];
+  int xk = 0;           // thread 0: ranges used up
+  unsigned claim = 0u;  // thread 0: claim in flight
+  if (threadIdx.x == 0) {
+    int b = 0, e = 0;
+    const int t0 = claim_resolve(claim_issue(flg, xk), starts, flg, P.per_xcd, P.ntiles, xk, b, e);
+    s_q[0][0] = t0;
+    s_q[0][1] = b;
+    s_q[0][2] = e;
+    const int t1 = t0 < 0 ? -1 : claim_resolve(claim_issue(flg, xk), starts, flg, P.per_xcd, P.ntiles, xk, b, e);
+    s_q[1][0] = t1;
+    s_q[1][1] = b;
+    s_q[1][2] = e;
   }
   __syncthreads();
+  int tile = __builtin_amdgcn_readfirstlane(s_q[0][0]);
+  if (tile < 0) return;
+  int pbeg = __builtin_amdgcn_readfirstlane(s_q[0][1]);
+  int pend = __builtin_amdgcn_readfirstlane(s_q[0][2]);
+  constexpr int NR = (G::e_vol + G::NT - 1) / G::NT;
+  R stage[NR][6];
+  int org[3];
+  tile_origin<DIMS, ORDER, R>(P, tile, org);
+  stage_load<DIMS, ORDER, R, NR>(P, F, org, stage);
+  for (int idx = threadIdx.x; idx < 3 * G::j_vol; idx += G::NT) s_j[idx] = 0.0;
 
-  const int lane = threadIdx.x & 63;
-  const int qb = (threadIdx.x >> 6) * Q::CAP;  // this wavefront's queue
-  int qn = 0;                                  // queued records (wavefront-uniform)
-  LdsCurrent<DIMS, ORDER, R> qsink{s_j, 0, s_j};
-
-  // The loop is uniform per wavefront (lanes past the end are idle) so that
-  // whole-wavefront queue rounds see every lane.  The next particle's state
-  // is loaded one iteration ahead.
-  int p = pbeg + threadIdx.x;
-  PState<R> nxt;
-  if (p < pend) nxt = load_particle<DIMS, R>(pa, p, P.q_const);
-  for (; p - lane < pend; p += G::NT) {
-    PState<R> s = nxt;
-    if (p + G::NT < pend) nxt = load_particle<DIMS, R>(pa, p + G::NT, P.q_const);
-    bool valid = p < pend && s.cl >= 0;
-    int c3[3] = {0, 0, 0};
-    if (valid) valid = decode<DIMS, R>(P, s, c3, flg);
-    // position relative to the tile origin (periodic image inside the window)
-    int l[3] = {0, 0, 0};
-    bool fast = true;
+  for (int it = 0;; ++it) {
+    const int tid = opaque_tid();
 #pragma unroll
-    for (int d = 0; d < DIMS; ++d) {
-      const int Td = d == 2 ? G::TZ : G::T;
-      const int Ad = d == 2 ? G::AZ : G::A;
-      int v = c3[d] - org[d];
-      if (P.bc[d] == PIC_BC_PERIODIC) {
-        v = v < 0 ? v + P.n[d] : v;
-        if (v >= Td + Ad) v -= P.n[d];
+    for (int k = 0; k < NR; ++k) {
+      const int r = tid + k * G::NT;
+      if (r < G::e_vol) {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) s_eb[c * G::e_vol + r] = stage[k][c];
       }
-      l[d] = v;
-      fast = fast && v >= -Ad && v < Td + Ad;
     }
-    R o1[3] = {R(0), R(0), R(0)}, vz = R(0);
-    int sh[3] = {0, 0, 0};
-    if (G::fixed && pa.q && !(fabs(s.q) <= qmax && qmax_ok)) fast = false;
-    if (valid && !fast) {  // leave the state as it was; the global-memory kernel redoes it
-      deferred[atomicAdd(&flg->ndefer, 1u)] = p;
-      valid = false;
+    const int nslot = (it + 1) & 1;
+    const int next = __builtin_amdgcn_readfirstlane(s_q[nslot][0]);
+    const int nbeg = __builtin_amdgcn_readfirstlane(s_q[nslot][1]);
+    const int nend = __builtin_amdgcn_readfirstlane(s_q[nslot][2]);
+    if (threadIdx.x == 0) {
+      s_batch = 0;
+      if (next >= 0) claim = claim_issue(flg, xk);  // for tile i+2
     }
-    if (valid) {
-      LdsFields<DIMS, ORDER, R> acc{
-          (lds_ptr<const R>)s_eb, ((l[2] - G::e_lo_z) * G::ex + (l[1] - G::e_lo)) * G::ex + (l[0] - G::e_lo)};
-      R Ep[3], Bp[3];
-      gather<DIMS, ORDER, R>(acc, s.o, Ep, Bp);
-      bool small = false;
-      if (!push_move<DIMS, R>(P, s, Ep, Bp, sh, o1, vz, small, flg)) {
-        pa.cell[p] = -1;
-        valid = false;
-      } else if (!small) {
+
+    // Scales of the fixed-point current tile (single form).  A contribution
+    // to J_c is q jfac_c P A with |P| <= |move along c| < 1/2 and 0 <= A <= 1
+    // (P is a difference of the cumulative shape, A an average of products
+    // of weights), so |contribution| < qmax |jfac_c| / 2; in 2D J_z is
+    // q v_z f A with |v_z| < 1, f <= 1, so qmax bounds it.  A tile sample
+    // receives at most (DIMS+1) contributions per particle of the tile
+    // (2^g bounds their number).  The power-of-two scale 2^K keeps every
+    // sum below 2^47 and so every scaled contribution below 2^(47-g):
+    // contributions round to integers at 2^-(48-g) of the bound (about
+    // 2^-34 for the 3D 8^3 tiles at 8 particles per cell, far below single
+    // precision) and the 48-bit tile sums are exact.  A particle whose |q|
+    // exceeds the bound the sort recorded (charges changed since) takes the
+    // global-memory path.
+    R jf[3] = {P.jfac[0], P.jfac[1], P.jfac[2]};
+    R zs = R(1);
+    int Ks[3] = {0, 0, 0};
+    const float qmax = pa.q ? __uint_as_float(flg->qmax) : fabsf((float)P.q_const);
+    const bool qmax_ok = qmax <= 3.0e38f;
+    if constexpr (G::fixed) {
+      const unsigned ncontrib = (unsigned)(DIMS + 1) * (unsigned)(pend - pbeg);
+      const int g = 32 - __clz((int)(ncontrib - 1u));  // ncontrib <= 2^g
+      const int top = 47 - g;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const bool z2 = DIMS == 2 && c == 2;
+        int e = 0;
+        frexpf(z2 ? qmax : qmax * fabsf((float)P.jfac[c]) * 0.5f, &e);  // bound < 2^e
+        // uniform over the workgroup: keep the scales in scalar registers
+        Ks[c] = __builtin_amdgcn_readfirstlane(qmax_ok ? top - e : 0);
+        const float sc = ldexpf(z2 ? 1.0f : (float)P.jfac[c], Ks[c]);
+        const float su = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(sc)));
+        if (z2)
+          zs = su;
+        else
+          jf[c] = su;
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {  // tile i+2 (wavefront 0 starts its particles later)
+      int t2 = -1, b = 0, e = 0;
+      if (next >= 0) t2 = claim_resolve(claim, starts, flg, P.per_xcd, P.ntiles, xk, b, e);
+      s_q[it & 1][0] = t2;
+      s_q[it & 1][1] = b;
+      s_q[it & 1][2] = e;
+    }
+    const int lane = threadIdx.x & 63;
+    const int qb = (threadIdx.x >> 6) * Q::CAP;  // this wavefront's queue
+    int qn = 0;                                  // queued records (wavefront-uniform)
+    LdsCurrent<DIMS, ORDER, R> qsink{s_j, 0, s_j};
+
+    // Wavefronts take batches of 64 consecutive particles from a counter in
+    // LDS, so that the wavefronts the SIMD arbiter serves first take more
+    // and all finish together.  The loop is uniform per wavefront (lanes
+    // past the end are idle) so that whole-wavefront queue rounds see every
+    // lane.  The next batch is taken, and its particle state loaded, one
+    // iteration ahead.
+    int p = pbeg + 64 * take_batch(&s_batch) + lane, pn;
+    PState<R> nxt;
+    if (p < pend) nxt = load_particle<DIMS, R>(pa, p, P.q_const);
+    for (; p - lane < pend; p = pn) {
+      PState<R> s = nxt;
+      pn = pbeg + 64 * take_batch(&s_batch) + lane;
+      if (pn < pend) nxt = load_particle<DIMS, R>(pa, pn, P.q_const);
+      bool valid = p < pend && s.cl >= 0;
+      int c3[3] = {0, 0, 0};
+      if (valid) valid = decode<DIMS, R>(P, s, c3, flg);
+      // position relative to the tile origin (periodic image inside the window)
+      int l[3] = {0, 0, 0};
+      bool fast = true;
+#pragma unroll
+      for (int d = 0; d < DIMS; ++d) {
+        const int Td = d == 2 ? G::TZ : G::T;
+        const int Ad = d == 2 ? G::AZ : G::A;
+        int v = c3[d] - org[d];
+        if (P.bc[d] == PIC_BC_PERIODIC) {
+          v = v < 0 ? v + P.n[d] : v;
+          if (v >= Td + Ad) v -= P.n[d];
+        }
+        l[d] = v;
+        fast = fast && v >= -Ad && v < Td + Ad;
+      }
+      R o1[3] = {R(0), R(0), R(0)}, vz = R(0);
+      int sh[3] = {0, 0, 0};
+      if (G::fixed && pa.q && !(fabs(s.q) <= qmax && qmax_ok)) fast = false;
+      if (valid && !fast) {  // leave the state as it was; the global-memory kernel redoes it
         deferred[atomicAdd(&flg->ndefer, 1u)] = p;
         valid = false;
       }
-    }
-    Split<DIMS, R> S;
-    S.m = 0;
-    const int pbase = ((l[2] - G::j_lo_z) * G::jx + (l[1] - G::j_lo)) * G::jx + (l[0] - G::j_lo);
-    if (valid) {
-      split_path<DIMS, ORDER, R>(S, s.o, sh, o1);
-      R xa[3], xb[3], ft;
-      int base[3];
-      segment_ends<DIMS, ORDER, R>(S, 0, xa, xb, base, ft);
-      LdsCurrent<DIMS, ORDER, R> sink{s_j, pbase, s_j};
-      sink.segment(base);
-      deposit_segment<DIMS, ORDER, R>(sink, jf, xa, xb, s.q, s.q * vz * ft * zs);
-      store_particle<DIMS, R>(pa, p, s, o1, new_cell<DIMS, R>(P, c3, sh));
-    }
-    // segments after the first
-    const int nx = valid ? S.m : 0;
-    const unsigned long long b0 = __ballot(nx & 1), b1 = __ballot(nx & 2);
-    const int total = (int)(__popcll(b0) + 2 * __popcll(b1));
-    if (total == 0) continue;
-    if (Q::on && qn + total <= Q::CAP) {
-      const unsigned long long below = (1ull << lane) - 1ull;
-      int pos = qn + (int)(__popcll(b0 & below) + 2 * __popcll(b1 & below));
-      for (int sg = 1; sg <= nx; ++sg, ++pos) {
-        R xa[3], xb[3], ft;
-        int base[3];
-        segment_ends<DIMS, ORDER, R>(S, sg, xa, xb, base, ft);
-        q_idx[qb + pos] = pbase + (base[2] * G::jx + base[1]) * G::jx + base[0];
-        q_val[0][qb + pos] = s.q;
-        q_val[1][qb + pos] = s.q * vz * ft * zs;
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-          q_val[2 + d][qb + pos] = xa[d];
-          q_val[5 + d][qb + pos] = xb[d];
+      if (valid) {
+        LdsFields<DIMS, ORDER, R> acc{
+            (lds_ptr<const R>)s_eb, ((l[2] - G::e_lo_z) * G::ex + (l[1] - G::e_lo)) * G::ex + (l[0] - G::e_lo)};
+        R Ep[3], Bp[3];
+        gather<DIMS, ORDER, R>(acc, s.o, Ep, Bp);
+        bool small = false;
+        if (!push_move<DIMS, R>(P, s, Ep, Bp, sh, o1, vz, small, flg)) {
+          pa.cell[p] = -1;
+          valid = false;
+        } else if (!small) {
+          deferred[atomicAdd(&flg->ndefer, 1u)] = p;
+          valid = false;
         }
       }
-      qn += total;
-      while (qn >= 64) {  // one whole-wavefront round from the queue's end
-        __builtin_amdgcn_wave_barrier();
-        const int r = qb + qn - 64 + lane;
+      Split<DIMS, R> S;
+      S.m = 0;
+      const int pbase = ((l[2] - G::j_lo_z) * G::jx + (l[1] - G::j_lo)) * G::jx + (l[0] - G::j_lo);
+      if (valid) {
+        split_path<DIMS, ORDER, R>(S, s.o, sh, o1);
+        R xa[3], xb[3], ft;
+        int base[3];
+        segment_ends<DIMS, ORDER, R>(S, 0, xa, xb, base, ft);
+        LdsCurrent<DIMS, ORDER, R> sink{s_j, pbase, s_j};
+        sink.segment(base);
+        deposit_segment<DIMS, ORDER, R>(sink, jf, xa, xb, s.q, s.q * vz * ft * zs);
+        store_particle<DIMS, R>(pa, p, s, o1, new_cell<DIMS, R>(P, c3, sh));
+      }
+      // segments after the first
+      const int nx = valid ? S.m : 0;
+      const unsigned long long b0 = __ballot(nx & 1), b1 = __ballot(nx & 2);
+      const int total = (int)(__popcll(b0) + 2 * __popcll(b1));
+      if (total == 0) continue;
+      if (Q::on && qn + total <= Q::CAP) {
+        const unsigned long long below = (1ull << lane) - 1ull;
+        int pos = qn + (int)(__popcll(b0 & below) + 2 * __popcll(b1 & below));
+        for (int sg = 1; sg <= nx; ++sg, ++pos) {
+          R xa[3], xb[3], ft;
+          int base[3];
+          segment_ends<DIMS, ORDER, R>(S, sg, xa, xb, base, ft);
+          q_idx[qb + pos] = pbase + (base[2] * G::jx + base[1]) * G::jx + base[0];
+          q_val[0][qb + pos] = s.q;
+          q_val[1][qb + pos] = s.q * vz * ft * zs;
+#pragma unroll
+          for (int d = 0; d < 3; ++d) {
+            q_val[2 + d][qb + pos] = xa[d];
+            q_val[5 + d][qb + pos] = xb[d];
+          }
+        }
+        qn += total;
+        while (qn >= 64) {  // one whole-wavefront round from the queue's end
+          __builtin_amdgcn_wave_barrier();
+          const int r = qb + qn - 64 + lane;
+          const R xa[3] = {q_val[2][r], q_val[3][r], q_val[4][r]};
+          const R xb[3] = {q_val[5][r], q_val[6][r], q_val[7][r]};
+          qsink.seg = s_j + q_idx[r];
+          deposit_segment<DIMS, ORDER, R>(qsink, jf, xa, xb, q_val[0][r], q_val[1][r]);
+          __builtin_amdgcn_wave_barrier();
+          qn -= 64;
+        }
+      } else {  // queue full (or not available): deposit in place
+        LdsCurrent<DIMS, ORDER, R> sink{s_j, pbase, s_j};
+        for (int sg = 1; sg <= nx; ++sg) {
+          R xa[3], xb[3], ft;
+          int base[3];
+          segment_ends<DIMS, ORDER, R>(S, sg, xa, xb, base, ft);
+          sink.segment(base);
+          deposit_segment<DIMS, ORDER, R>(sink, jf, xa, xb, s.q, s.q * vz * ft * zs);
+        }
+      }
+    }
+    if (Q::on && qn > 0) {  // drain the queue
+      __builtin_amdgcn_wave_barrier();
+      if (lane < qn) {
+        const int r = qb + lane;
         const R xa[3] = {q_val[2][r], q_val[3][r], q_val[4][r]};
         const R xb[3] = {q_val[5][r], q_val[6][r], q_val[7][r]};
         qsink.seg = s_j + q_idx[r];
         deposit_segment<DIMS, ORDER, R>(qsink, jf, xa, xb, q_val[0][r], q_val[1][r]);
-        __builtin_amdgcn_wave_barrier();
-        qn -= 64;
-      }
-    } else {  // queue full (or not available): deposit in place
-      LdsCurrent<DIMS, ORDER, R> sink{s_j, pbase, s_j};
-      for (int sg = 1; sg <= nx; ++sg) {
-        R xa[3], xb[3], ft;
-        int base[3];
-        segment_ends<DIMS, ORDER, R>(S, sg, xa, xb, base, ft);
-        sink.segment(base);
-        deposit_segment<DIMS, ORDER, R>(sink, jf, xa, xb, s.q, s.q * vz * ft * zs);
       }
     }
-  }
-  if (Q::on && qn > 0) {  // drain the queue
-    __builtin_amdgcn_wave_barrier();
-    if (lane < qn) {
-      const int r = qb + lane;
-      const R xa[3] = {q_val[2][r], q_val[3][r], q_val[4][r]};
-      const R xb[3] = {q_val[5][r], q_val[6][r], q_val[7][r]};
-      qsink.seg = s_j + q_idx[r];
-      deposit_segment<DIMS, ORDER, R>(qsink, jf, xa, xb, q_val[0][r], q_val[1][r]);
-    }
-  }
-  __syncthreads();
-
-  // flush the LDS current tile (its halo overlaps the neighbouring tiles')
-  for (int r = threadIdx.x; r < G::j_vol; r += G::NT) {
-    const int lx = r % G::jx, ly = (r / G::jx) % G::jx, lz = r / (G::jx * G::jx);
-    int sx[2], sy[2], sz[2] = {0, 0};
-    axis_slots(org[0] + G::j_lo + lx, P.n[0], open0, 1, sx);
-    axis_slots(org[1] + G::j_lo + ly, P.n[1], open1, str1, sy);
-    if (DIMS == 3) axis_slots(org[2] + G::j_lo_z + lz, P.n[2], open2, str2, sz);
+    // (the opaque copy keeps the compiler from forming the next tile's
+    // addresses before the particle loop, where registers are scarce)
+    int nt = next;
+    asm volatile("" : "+s"(nt));
+    if (nt >= 0) {  // the next tile's fields, in flight during the flush
+      int norg[3];
+      tile_origin<DIMS, ORDER, R>(P, nt, norg);
+      stage_load<DIMS, ORDER, R, NR>(P, F, norg, stage);
+    } else {  // (defining stage on both paths ends the current values' life here)
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {  // J_c staggered along c
-      R v;
-      if constexpr (G::fixed)
-        v = (R)ldexp((double)((const long long*)s_j)[c * G::j_vol + r], -Ks[c]);
-      else
-        v = (R)s_j[c * G::j_vol + r];
-      const int ix = sx[c == 0], iy = sy[c == 1], iz = sz[c == 2];
-      if (v != R(0) && ix >= 0 && iy >= 0 && iz >= 0) atomic_add(&F.J[c][ix + iy + iz], v);
+      for (int k = 0; k < NR; ++k)
+#pragma unroll
+        for (int c = 0; c < 6; ++c) stage[k][c] = R(0);
     }
+    __syncthreads();
+
+    // flush the LDS current tile (its halo overlaps the neighbouring
+    // tiles') and clear it for the next tile
+    const int jbx = org[0] + G::j_lo, jby = org[1] + G::j_lo, jbz = org[2] + G::j_lo_z;
+    if (axis_inside(jbx, G::jx, P.n[0], open0) && axis_inside(jby, G::jx, P.n[1], open1) &&
+        (DIMS == 2 || axis_inside(jbz, G::jz, P.n[2], open2))) {
+      const int base = (DIMS == 3 ? jbz * str2 : 0) + jby * str1 + jbx;
+      for (int r = opaque_tid(); r < G::j_vol; r += G::NT) {
+        const int lx = r % G::jx, ly = (r / G::jx) % G::jx, lz = r / (G::jx * G::jx);
+        const int o = base + (DIMS == 3 ? lz * str2 : 0) + ly * str1 + lx;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          R v;
+          if constexpr (G::fixed)
+            v = (R)ldexp((double)sext48(((const long long*)s_j)[c * G::j_vol + r]), -Ks[c]);
+          else
+            v = (R)s_j[c * G::j_vol + r];
+          s_j[c * G::j_vol + r] = 0.0;
+          if (v != R(0)) atomic_add(&F.J[c][o], v);
+        }
+      }
+    } else {
+      for (int r = opaque_tid(); r < G::j_vol; r += G::NT) {
+        const int lx = r % G::jx, ly = (r / G::jx) % G::jx, lz = r / (G::jx * G::jx);
+        int sx[2], sy[2], sz[2] = {0, 0};
+        axis_slots(org[0] + G::j_lo + lx, P.n[0], open0, 1, sx);
+        axis_slots(org[1] + G::j_lo + ly, P.n[1], open1, str1, sy);
+        if (DIMS == 3) axis_slots(org[2] + G::j_lo_z + lz, P.n[2], open2, str2, sz);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {  // J_c staggered along c
+          R v;
+          if constexpr (G::fixed)
+            v = (R)ldexp((double)sext48(((const long long*)s_j)[c * G::j_vol + r]), -Ks[c]);
+          else
+            v = (R)s_j[c * G::j_vol + r];
+          s_j[c * G::j_vol + r] = 0.0;
+          const int ix = sx[c == 0], iy = sy[c == 1], iz = sz[c == 2];
+          if (v != R(0) && ix >= 0 && iy >= 0 && iz >= 0) atomic_add(&F.J[c][ix + iy + iz], v);
+        }
+      }
+    }
+    if (next < 0) break;
+    tile = next;
+    pbeg = nbeg;
+    pend = nend;
+    tile_origin<DIMS, ORDER, R>(P, tile, org);
   }
 }
 
@@ -319,16 +489,48 @@ __global__ void __launch_bounds__(256) k_push_deferred(KParams<R> P, DParts<R> p
   if (blockIdx.x == 0 && threadIdx.x == 0 && nd > 0) atomicAdd(&flg->slowpath, (unsigned long long)nd);
 }
 
-// Zero J (n = 0: keep it, another species adds its current) and the
-// deferred-list length before a push.
+// Zero J (n = 0: keep it, another species adds its current), the
+// deferred-list length and the tile counters before a push.
 template <typename R>
 __global__ void k_push_prologue(R* a, R* b, R* c, long n, DevFlags* flg) {
   if (blockIdx.x == 0 && threadIdx.x == 0) flg->ndefer = 0u;
+  if (blockIdx.x == 0 && threadIdx.x < 8) flg->tile_next[threadIdx.x] = 0u;
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
     a[i] = R(0);
     b[i] = R(0);
     c[i] = R(0);
   }
+}
+
+static int device_cus() {
+  static int cache[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (cache[dev] == 0) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0)
+      n = 256;
+    cache[dev] = n;
+  }
+  return cache[dev];
+}
+
+// Workgroups of the persistent tile kernel: as many as are resident at once
+// (compute units x workgroups per unit), at most 8 x the XCD range length.
+template <int DIMS, int ORDER, typename R>
+static unsigned tile_grid(const KParams<R>& P) {
+  using G = Geo<DIMS, ORDER, R>;
+  static int occ = 0;
+  if (occ == 0) {
+    int b = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_push_tile<DIMS, ORDER, R>, G::NT, 0) !=
+            hipSuccess ||
+        b < 1)
+      b = 1;
+    occ = b;
+  }
+  const long want = 8L * P.per_xcd, have = (long)device_cus() * occ;
+  return (unsigned)(want < have ? want : have);
 }
 
 template <int DIMS, int ORDER, typename R>
@@ -358,7 +560,7 @@ static int launch_pd(const pic_ctx* ctx, const pic_particles* p, const pic_field
   const long fb = (ncell + 255) / 256;
   k_push_prologue<R><<<dim3((unsigned)(fb < 1 ? 1 : fb < 4096 ? fb : 4096)), dim3(256), 0, s>>>(
       F.J[0], F.J[1], F.J[2], ncell, flg);
-  k_push_tile<DIMS, ORDER, R><<<dim3(8 * P.per_xcd), dim3(G::NT), 0, s>>>(
+  k_push_tile<DIMS, ORDER, R><<<dim3(tile_grid<DIMS, ORDER, R>(P)), dim3(G::NT), 0, s>>>(
       P, pa, F, (const int*)(w + L.starts), deferred, flg);
   k_push_deferred<DIMS, ORDER, R><<<dim3(1024), dim3(256), 0, s>>>(P, pa, F, deferred, flg);
   return (int)hipGetLastError();

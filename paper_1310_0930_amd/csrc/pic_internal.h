@@ -128,8 +128,12 @@ struct DevFlags {
   // largest |q| (as float) over the per-particle charges it moved.
   unsigned int qmax;
   unsigned int pad1;
-  unsigned long long pad2[5];
+  // Work counters of the persistent push: tiles taken so far from each
+  // XCD's tile range (cleared before every push).
+  unsigned int tile_next[8];
+  unsigned long long pad2[1];
 };
+static_assert(sizeof(DevFlags) == 64, "DevFlags layout");
 
 // ------------------------------------------------------------------ workspace
 // The sort bins particles by (tile, rank within the cell), SORT_RANKS rank
