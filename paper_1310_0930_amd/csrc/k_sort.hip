@@ -1,25 +1,30 @@
-// Tile sort of the SoA particle arrays: counting sort on (tile of the
-// particle's cell, rank of the particle within its cell); absorbed
-// particles go to a last, dead bin.
+// Tile sort of the SoA particle arrays, in two levels: a counting sort on
+// the tile of the particle's cell (absorbed particles go to a last, dead
+// bin), then, inside every tile, a placement by (class, rank within the
+// cell and class, cell).
 //
 // Not a step of the paper's method: it is the data layout that makes the
 // fused push/deposit local (one workgroup per tile, fields and currents in
 // LDS), the GPU counterpart of the paper's per-node particle partition
 // (Sec. 3) and of its answer to deposit write conflicts (Sec. 3.1, Sec. 5.2).
 //
-// Inside a tile the particles come rank by rank: first one particle of
-// every cell, then a second one of every cell that has two, and so on, so a
-// wavefront's 64 lanes sit in different cells and their LDS accesses spread
-// over the banks.  Ranks come from per-cell counters (clamped to RB - 1).
-// Particles with equal keys are mostly contiguous already (they were
-// sorted before and drift slowly), so the rank counters, the histogram and
-// the scatter aggregate runs of equal values inside a wavefront: one global
-// atomic per run instead of one per particle.
+// Inside a tile the particles come class by class and, within a class,
+// rank by rank: first one particle of every cell that has one in that
+// class (in cell order), then a second one, and so on.  The class is the
+// half of the cell the particle sits in along each axis (offset >= 1/2 or
+// not), which fixes the first stencil node of every field and current
+// component relative to the cell; so a wavefront's 64 lanes sit in
+// neighbouring, distinct cells with the same stencil shape, and their LDS
+// reads and atomics spread over the banks instead of colliding where
+// neighbouring lanes' stencils are shifted by one node against each other.
+// The tile-level pass aggregates runs of equal tiles inside a wavefront
+// (particles stay in their tile for many steps), one global atomic per run;
+// the placement runs in LDS, one workgroup per tile.
 #include "k_common.h"
 
 namespace pic {
 
-constexpr int RB = SORT_RANKS;
+constexpr int NB = SORT_BINS;
 
 struct SortParams {
   int n[3];
@@ -50,7 +55,8 @@ __device__ __forceinline__ int tile_key(const SortParams& S, int cl, int ncell) 
 // Run structure of the keys held by one wavefront: a lane starts a run when
 // its key differs from the previous lane's.  Returns the run's first lane and
 // its length (for the first lane).
-__device__ __forceinline__ void wave_runs(int key, int& head_lane, int& run_len) {
+template <typename K>
+__device__ __forceinline__ void wave_runs(K key, int& head_lane, int& run_len) {
   const int lane = threadIdx.x & 63;
   const int prev = __shfl_up(key, 1, 64);
   const bool boundary = lane == 0 || key != prev;
@@ -64,23 +70,25 @@ __device__ __forceinline__ void wave_runs(int key, int& head_lane, int& run_len)
   run_len = next - head_lane;
 }
 
-// Rank within the cell (run-aggregated per-cell counters), bin key
-// tile * RB + min(rank, RB - 1), and the histogram of the keys.
+// Workgroup b of n takes chunk (b * M) mod n (M prime; a permutation of
+// the chunks unless M divides n).  Sorted particles of one tile are
+// contiguous, so in block order the wavefronts running together would all
+// add to the same bin counter or cursor, and same-address device atomics
+// serialize; in this order they spread over many tiles.
+__device__ __forceinline__ long spread_block(unsigned b, unsigned n) {
+  constexpr unsigned long long M = 1000003ull;
+  return n % M == 0 ? (long)b : (long)(((unsigned long long)b * M) % n);
+}
+
+// Tile key of every particle (ntiles: dead) and the histogram of the keys.
 __global__ void k_sort_count(SortParams S, const int* __restrict__ cell, long np, int ncell,
-                             int* __restrict__ cellcnt, int* __restrict__ keys,
-                             int* __restrict__ counts, DevFlags* flg) {
-  const long p = blockIdx.x * (long)blockDim.x + threadIdx.x;
+                             int* __restrict__ keys, int* __restrict__ counts, DevFlags* flg) {
+  const long p = spread_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (p == 0) flg->qmax = 0u;  // the scatter (next launch) takes the new maximum
   const int lane = threadIdx.x & 63;
-  const int cl = p < np ? cell[p] : -1;
-  const bool live = cl >= 0 && cl < ncell;
-  int head, len;
-  wave_runs(live ? cl : -1 - (int)(p < np), head, len);
-  int rank = 0;
-  if (live && lane == head) rank = atomicAdd(&cellcnt[cl], len);
-  rank = __shfl(rank, head, 64) + (lane - head);
-  const int key = p >= np ? -1 : live ? tile_key(S, cl, ncell) * RB + min(rank, RB - 1) : S.ntiles * RB;
+  const int key = p < np ? tile_key(S, cell[p], ncell) : -1;
   if (p < np) keys[p] = key;
+  int head, len;
   wave_runs(key, head, len);
   if (lane == head && key >= 0) atomicAdd(&counts[key], len);
 }
@@ -145,8 +153,7 @@ __global__ void __launch_bounds__(SCAN_B) k_scan_apply(int* __restrict__ counts,
 // (t = ntiles: first absorbed particle), tstart[ntiles + 1] = np.
 __global__ void k_tile_starts(const int* __restrict__ bstart, int ntiles, int* __restrict__ tstart) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t <= ntiles) tstart[t] = bstart[t * RB];
-  if (t == ntiles + 1) tstart[t] = bstart[ntiles * RB + 1];
+  if (t <= ntiles + 1) tstart[t] = bstart[t];
 }
 
 template <typename R>
@@ -167,7 +174,7 @@ template <typename R>
 __global__ void k_sort_scatter(SortArrays<R> A, long np, int ncell, int dims,
                                const int* __restrict__ keys, int* __restrict__ cursor,
                                DevFlags* flg) {
-  const long p = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  const long p = spread_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   const bool in = p < np;
   // the payload is loaded first, so that its latency overlaps the cursor
   // atomic's round trip
@@ -209,14 +216,134 @@ __global__ void k_sort_scatter(SortArrays<R> A, long np, int ncell, int dims,
   if (A.q) A.t_q[dst] = qv;
 }
 
+// Copy of particle i of the scatter's arrays to slot j of the particle
+// arrays: every load first, then every store (a store to one array may
+// alias a later load of another as far as the compiler knows, which would
+// serialize the round trips).
 template <typename R>
-__global__ void k_sort_copyback(SortArrays<R> A, long np, int dims) {
-  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < np; i += (long)gridDim.x * blockDim.x) {
-    const_cast<int*>(A.cell)[i] = A.t_cell[i];
-    for (int d = 0; d < dims; ++d) const_cast<R*>(A.off[d])[i] = A.t_off[d][i];
-    for (int c = 0; c < 3; ++c) const_cast<R*>(A.u[c])[i] = A.t_u[c][i];
-    if (A.q) const_cast<R*>(A.q)[i] = A.t_q[i];
-    if (A.id) const_cast<int*>(A.id)[i] = A.t_id[i];
+__device__ __forceinline__ void copy_back(const SortArrays<R>& A, long i, long j, int dims) {
+  const int cl = A.t_cell[i];
+  R o[3] = {R(0), R(0), R(0)}, u[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+    if (d < dims) o[d] = A.t_off[d][i];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) u[c] = A.t_u[c][i];
+  const R qv = A.q ? A.t_q[i] : R(0);
+  const int idv = A.id ? A.t_id[i] : 0;
+  const_cast<int*>(A.cell)[j] = cl;
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+    if (d < dims) const_cast<R*>(A.off[d])[j] = o[d];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) const_cast<R*>(A.u[c])[j] = u[c];
+  if (A.q) const_cast<R*>(A.q)[j] = qv;
+  if (A.id) const_cast<int*>(A.id)[j] = idv;
+}
+
+// Copy back of the dead bin (absorbed particles, in scatter order).
+template <typename R>
+__global__ void k_sort_copyback_dead(SortArrays<R> A, const int* __restrict__ dead_start, long np,
+                                     int dims) {
+  for (long i = *dead_start + blockIdx.x * (long)blockDim.x + threadIdx.x; i < np;
+       i += (long)gridDim.x * blockDim.x)
+    copy_back(A, i, i, dims);
+}
+
+// Placement of one tile's particles (one workgroup per tile) from the
+// scatter's copy back into the particle arrays.  Pass 1 gives every particle
+// its class and its rank within (cell, class) from LDS counters, and counts
+// the tile's NB bins (class, min(rank, last bucket)); pass 2 puts each
+// particle at its bin's start plus its place in the bin: in a bin below the
+// class's last rank bucket every cell appears once, so the k-th cell of the
+// bin (in cell order, from a bit mask of the bin's cells) takes slot k; the
+// last bucket is filled in arrival order.
+constexpr int PLACE_NT = 1024;
+constexpr int TILE_CELLS_MAX = 512;
+template <typename R>
+__global__ void __launch_bounds__(PLACE_NT) k_sort_place(SortArrays<R> A, SortParams S,
+                                                          const int* __restrict__ tstart,
+                                                          int* __restrict__ scratch, int dims) {
+  constexpr int W = TILE_CELLS_MAX / 32;  // mask words per bin
+  __shared__ int cnt[TILE_CELLS_MAX * 8];
+  __shared__ unsigned mask[NB][W];
+  __shared__ int pre[NB][W];
+  __shared__ int binc[NB];
+  __shared__ int bin0[NB];
+  const int t = blockIdx.x;
+  const int beg = tstart[t], end = tstart[t + 1];
+  if (beg == end) return;
+  for (int i = threadIdx.x; i < TILE_CELLS_MAX * 8; i += PLACE_NT) cnt[i] = 0;
+  for (int i = threadIdx.x; i < NB * W; i += PLACE_NT) (&mask[0][0])[i] = 0u;
+  for (int i = threadIdx.x; i < NB; i += PLACE_NT) binc[i] = 0;
+  __syncthreads();
+  const int tx = t % S.ntile[0], ty = (t / S.ntile[0]) % S.ntile[1], tz = t / (S.ntile[0] * S.ntile[1]);
+  const int rb = NB >> dims;  // rank buckets per class
+  // (wavefront-uniform loop: the mask update below shuffles across lanes)
+  const int lane = threadIdx.x & 63;
+  for (int i = beg + threadIdx.x; i - lane < end; i += PLACE_NT) {
+    const bool in = i < end;
+    int b = 0, lc = 0, rank = 0;
+    if (in) {
+      const int cl = A.t_cell[i];
+      const uint32_t rest = S.dn0.div((uint32_t)cl);
+      const int cx = cl - (int)rest * S.n[0];
+      int cy = (int)rest, cz = 0;
+      if (dims == 3) {
+        const uint32_t r2 = S.dn1.div(rest);
+        cy = (int)(rest - r2 * S.n[1]);
+        cz = (int)r2;
+      }
+      lc = (cx - tx * S.T[0]) + S.T[0] * ((cy - ty * S.T[1]) + S.T[1] * (cz - tz * S.T[2]));
+      int cls = (A.t_off[0][i] >= R(0.5) ? 1 : 0) | (A.t_off[1][i] >= R(0.5) ? 2 : 0);
+      if (dims == 3) cls |= A.t_off[2][i] >= R(0.5) ? 4 : 0;
+      rank = atomicAdd(&cnt[cls * TILE_CELLS_MAX + lc], 1);  // (class-major: lanes of a class hit consecutive banks)
+      b = cls * rb + min(rank, rb - 1);
+      if (rank >= rb - 1) atomicAdd(&binc[b], 1);  // the last bucket's count (others: popcounts)
+      scratch[i] = b * TILE_CELLS_MAX + lc;
+    }
+    // mask bits of the bins below the last bucket, OR-ed over runs of lanes
+    // that share a mask word (neighbouring cells of one bin): one LDS atomic
+    // per run instead of one per lane on the same word
+    const bool mk = in && rank < rb - 1;
+    const int word = mk ? b * W + (lc >> 5) : -1 - lane;
+    int head, len;
+    wave_runs(word, head, len);
+    unsigned bits = mk ? 1u << (lc & 31) : 0u;
+    for (int off = 1; off < 64; off <<= 1) {
+      const unsigned v = __shfl_up(bits, off, 64);
+      if (lane - off >= head) bits |= v;
+    }
+    bits = __shfl(bits, head + len - 1, 64);
+    if (mk && lane == head) atomicOr(&(&mask[0][0])[word], bits);
+  }
+  __syncthreads();
+  if (threadIdx.x < NB) {
+    int acc = 0;
+    for (int w = 0; w < W; ++w) {
+      pre[threadIdx.x][w] = acc;
+      acc += __popc(mask[threadIdx.x][w]);
+    }
+    if (threadIdx.x % rb < rb - 1) binc[threadIdx.x] = acc;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int acc = beg;
+    for (int b = 0; b < NB; ++b) {
+      bin0[b] = acc;
+      acc += binc[b];
+    }
+  }
+  __syncthreads();
+  for (int i = beg + threadIdx.x; i < end; i += PLACE_NT) {
+    const int v = __builtin_nontemporal_load(&scratch[i]);
+    const int b = v / TILE_CELLS_MAX, lc = v % TILE_CELLS_MAX;
+    int j;
+    if (b % rb < rb - 1)
+      j = bin0[b] + pre[b][lc >> 5] + __popc(mask[b][lc >> 5] & ((1u << (lc & 31)) - 1u));
+    else
+      j = atomicAdd(&bin0[b], 1);  // last bucket (no mask): arrival order
+    copy_back(A, i, j, dims);
   }
 }
 
@@ -249,9 +376,8 @@ static int launch_sort_t(const pic_ctx* ctx, const pic_particles* p, void* ws, h
   int* starts = (int*)(w + L.starts);
   int* bstart = (int*)(w + L.bstart);
   int* bsum = (int*)(w + L.bsum);
-  int* cellcnt = (int*)(w + L.cellcnt);
   int* keys = (int*)(w + L.keys);
-  const int nb = S.ntiles * RB + 1;  // + dead bin
+  const int nb = S.ntiles + 1;  // + dead bin
   const int nblk = (nb + SCAN_B - 1) / SCAN_B;
   if (np == 0) {
     k_fill_int<<<dim3((S.ntiles + 2 + 255) / 256), dim3(256), 0, s>>>(starts, S.ntiles + 2, 0);
@@ -259,10 +385,9 @@ static int launch_sort_t(const pic_ctx* ctx, const pic_particles* p, void* ws, h
   }
   auto fill_grid = [](long n) { return dim3((unsigned)((n + 255) / 256 < 16384 ? (n + 255) / 256 : 16384)); };
   k_fill_int<<<fill_grid(nb), dim3(256), 0, s>>>(counts, nb, 0);
-  k_fill_int<<<fill_grid(ncell), dim3(256), 0, s>>>(cellcnt, ncell, 0);
   const unsigned grid = (unsigned)((np + 255) / 256);
   DevFlags* flg = (DevFlags*)(w + L.flags);
-  k_sort_count<<<dim3(grid), dim3(256), 0, s>>>(S, p->cell, np, ncell, cellcnt, keys, counts, flg);
+  k_sort_count<<<dim3(grid), dim3(256), 0, s>>>(S, p->cell, np, ncell, keys, counts, flg);
   k_scan_sums<<<dim3(nblk), dim3(SCAN_B), 0, s>>>(counts, nb, bsum);
   k_scan_blocks<<<dim3(1), dim3(SCAN_B), 0, s>>>(bsum, nblk);
   k_scan_apply<<<dim3(nblk), dim3(SCAN_B), 0, s>>>(counts, nb, bsum, bstart);
@@ -282,8 +407,9 @@ static int launch_sort_t(const pic_ctx* ctx, const pic_particles* p, void* ws, h
   A.t_cell = (int*)(w + L.tmp_cell);
   A.t_id = (int*)(w + L.tmp_id);
   k_sort_scatter<R><<<dim3(grid), dim3(256), 0, s>>>(A, np, ncell, c.dims, keys, counts, flg);
+  k_sort_place<R><<<dim3((unsigned)S.ntiles), dim3(PLACE_NT), 0, s>>>(A, S, starts, keys, c.dims);
   const unsigned g2 = grid < 8192 ? grid : 8192;
-  k_sort_copyback<R><<<dim3(g2), dim3(256), 0, s>>>(A, np, c.dims);
+  k_sort_copyback_dead<R><<<dim3(g2), dim3(256), 0, s>>>(A, starts + S.ntiles, np, c.dims);
   return (int)hipGetLastError();
 }
 

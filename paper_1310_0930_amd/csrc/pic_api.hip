@@ -23,9 +23,7 @@ WsLayout ws_layout(const pic_ctx* ctx, int64_t np) {
   size_t off = 0;
   L.flags = off;
   off = align256(off + sizeof(DevFlags));
-  const size_t nbins = (size_t)ctx->ntiles * SORT_RANKS + 1;
-  size_t ncell = 1;
-  for (int d = 0; d < ctx->cfg.dims; ++d) ncell *= (size_t)ctx->cfg.n[d];
+  const size_t nbins = (size_t)ctx->ntiles + 1;
   L.starts = off;
   off = align256(off + sizeof(int) * ((size_t)ctx->ntiles + 2));
   L.counts = off;
@@ -34,8 +32,6 @@ WsLayout ws_layout(const pic_ctx* ctx, int64_t np) {
   off = align256(off + sizeof(int) * (nbins + 1));
   L.bsum = off;
   off = align256(off + sizeof(int) * (nbins / 1024 + 1));
-  L.cellcnt = off;
-  off = align256(off + sizeof(int) * ncell);
   L.mur_len = (size_t)mur_len(ctx->cfg);
   L.mur = off;
   off = align256(off + R * L.mur_len);

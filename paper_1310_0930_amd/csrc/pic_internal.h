@@ -136,9 +136,11 @@ struct DevFlags {
 static_assert(sizeof(DevFlags) == 64, "DevFlags layout");
 
 // ------------------------------------------------------------------ workspace
-// The sort bins particles by (tile, rank within the cell), SORT_RANKS rank
-// buckets per tile, plus one dead bin.
-constexpr int SORT_RANKS = 16;
+// Inside a tile the sort orders particles by (class, rank within the cell
+// and class, cell) in SORT_BINS bins: the class of a particle is which half
+// of its cell it sits in along each axis (2^dims classes), with
+// SORT_BINS / 2^dims rank buckets per class.
+constexpr int SORT_BINS = 32;
 
 struct WsLayout {
   size_t flags;      // DevFlags
@@ -146,8 +148,7 @@ struct WsLayout {
   size_t counts;     // int32[nbins]        bin counts / scatter cursors
   size_t bstart;     // int32[nbins + 1]    bin starts
   size_t bsum;       // int32[nbins / 1024 + 1]  scan block sums
-  size_t cellcnt;    // int32[ncell]        particles per cell (ranks)
-  size_t keys;       // int32[np]           bin of each particle
+  size_t keys;       // int32[np]           tile of each particle, then its in-tile bin and cell
   size_t tmp_cell;   // int32[np]
   size_t tmp_real;   // R[np * 7]  off[3], u[3], q
   size_t tmp_id;     // int32[np]

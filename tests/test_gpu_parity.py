@@ -228,7 +228,7 @@ def test_fdtd_eigenmode_fp64():
 
 
 # ---------------------------------------------------------------- edge cases
-def test_sort_groups_by_tile_and_rank_and_keeps_a_permutation():
+def test_sort_groups_by_tile_class_and_rank_and_keeps_a_permutation():
     w = I.Workload("w3d_sort", 3, (40, 24, 16), (0.2, 0.2, 0.2), 2, 3, 0.3, 1,
                    seed=I.SEED_BASE + 70)
     pl, E, B = inputs_for(w)
@@ -249,16 +249,27 @@ def test_sort_groups_by_tile_and_rank_and_keeps_a_permutation():
     tx, ty, tz = (c % 40) // T, (c // 40) % 24 // T, c // (40 * 24) // T
     key = tx + 5 * (ty + 3 * tz)
     assert np.all(np.diff(key) >= 0)
-    # inside a tile the particles come rank by rank: the k-th particle of
-    # every cell before any (k+1)-th one (ranks from 15 on share a bucket)
+    # inside a tile the particles come class by class (class bit d: offset
+    # along d >= 1/2), and within a class rank by rank: the k-th particle of
+    # every cell in that class before any (k+1)-th one (32 bins per tile:
+    # 8 classes x 4 rank buckets, ranks from 3 on share a bucket)
+    o = st["off"]
+    cls = (o[0] >= 0.5).astype(np.int64) + 2 * (o[1] >= 0.5) + 4 * (o[2] >= 0.5)
     for t in np.unique(key):
-        cells = c[key == t]
+        m = key == t
+        cells, kt = c[m], cls[m]
+        assert np.all(np.diff(kt) >= 0), t
         seen = {}
         rank = np.empty(cells.size, dtype=np.int64)
-        for i, cl in enumerate(cells):
-            rank[i] = seen.get(cl, 0)
-            seen[cl] = rank[i] + 1
-        assert np.all(np.diff(np.minimum(rank, 15)) >= 0), t
+        for i, (cl, k) in enumerate(zip(cells, kt)):
+            rank[i] = seen.get((cl, k), 0)
+            seen[(cl, k)] = rank[i] + 1
+        for k in np.unique(kt):
+            assert np.all(np.diff(np.minimum(rank[kt == k], 3)) >= 0), (t, k)
+            # a bin below the last rank bucket holds each cell once, in cell order
+            for r in range(3):
+                cb = cells[(kt == k) & (rank == r)]
+                assert np.all(np.diff(cb) > 0), (t, k, r)
 
 
 def test_empty_and_ragged_particle_counts():
