@@ -34,6 +34,10 @@ struct SortParams {
   int ntiles;
   int dims;
   FastDiv dn0, dn1;
+  // the push kernel's LDS field region: row and plane strides (elements) and
+  // the number of distinct bank positions of an element (32 four-byte
+  // banks: 32 for single, 16 for double precision)
+  int rs1, rs2, rmod;
 };
 
 __device__ __forceinline__ int tile_key(const SortParams& S, int cl, int ncell) {
@@ -250,6 +254,40 @@ __global__ void k_sort_copyback_dead(SortArrays<R> A, const int* __restrict__ de
     copy_back(A, i, i, dims);
 }
 
+// In-bin order of a tile's cells.  A bin's cells hold one particle each
+// with one stencil shape, so in the push every LDS access of a wavefront is
+// the lanes' cell base addresses plus one common offset; lanes whose bases
+// fall on the same bank serialize.  Cells are ranked by (k, r) where r is
+// the bank position of the cell's base in the field region and k counts
+// the earlier cells with the same r: consecutive cells of the order cycle
+// through the bank positions, and so do consecutive lanes of a bin that
+// holds most of the tile's cells.  One workgroup; order[lc] = rank of cell
+// lc.
+constexpr int ORDER_NT = 512;
+__global__ void __launch_bounds__(ORDER_NT) k_sort_order(SortParams S, int* __restrict__ order) {
+  __shared__ int cnt[32];
+  const int ncells = S.T[0] * S.T[1] * S.T[2];
+  const int lc = threadIdx.x;
+  if (lc < 32) cnt[lc] = 0;
+  __syncthreads();
+  auto residue = [&](int c) {
+    const int lx = c % S.T[0], ly = (c / S.T[0]) % S.T[1], lz = c / (S.T[0] * S.T[1]);
+    return (lx + S.rs1 * ly + S.rs2 * lz) % S.rmod;
+  };
+  int r = 0, k = 0;
+  if (lc < ncells) {
+    r = residue(lc);
+    atomicAdd(&cnt[r], 1);
+    for (int c = 0; c < lc; ++c) k += residue(c) == r;
+  }
+  __syncthreads();
+  if (lc < ncells) {
+    int pos = 0;
+    for (int q = 0; q < S.rmod; ++q) pos += min(cnt[q], k) + (q < r && cnt[q] > k ? 1 : 0);
+    order[lc] = pos;
+  }
+}
+
 // Placement of one tile's particles (one workgroup per tile) from the
 // scatter's copy back into the particle arrays.  Pass 1 gives every particle
 // its class and its rank within (cell, class) from LDS counters, and counts
@@ -263,6 +301,7 @@ constexpr int TILE_CELLS_MAX = 512;
 template <typename R>
 __global__ void __launch_bounds__(PLACE_NT) k_sort_place(SortArrays<R> A, SortParams S,
                                                           const int* __restrict__ tstart,
+                                                          const int* __restrict__ order,
                                                           int* __restrict__ scratch, int dims) {
   constexpr int W = TILE_CELLS_MAX / 32;  // mask words per bin
   __shared__ int cnt[TILE_CELLS_MAX * 8];
@@ -270,9 +309,11 @@ __global__ void __launch_bounds__(PLACE_NT) k_sort_place(SortArrays<R> A, SortPa
   __shared__ int pre[NB][W];
   __shared__ int binc[NB];
   __shared__ int bin0[NB];
+  __shared__ int ord[TILE_CELLS_MAX];
   const int t = blockIdx.x;
   const int beg = tstart[t], end = tstart[t + 1];
   if (beg == end) return;
+  for (int i = threadIdx.x; i < TILE_CELLS_MAX; i += PLACE_NT) ord[i] = order[i];
   for (int i = threadIdx.x; i < TILE_CELLS_MAX * 8; i += PLACE_NT) cnt[i] = 0;
   for (int i = threadIdx.x; i < NB * W; i += PLACE_NT) (&mask[0][0])[i] = 0u;
   for (int i = threadIdx.x; i < NB; i += PLACE_NT) binc[i] = 0;
@@ -294,10 +335,11 @@ __global__ void __launch_bounds__(PLACE_NT) k_sort_place(SortArrays<R> A, SortPa
         cy = (int)(rest - r2 * S.n[1]);
         cz = (int)r2;
       }
-      lc = (cx - tx * S.T[0]) + S.T[0] * ((cy - ty * S.T[1]) + S.T[1] * (cz - tz * S.T[2]));
+      const int cell = (cx - tx * S.T[0]) + S.T[0] * ((cy - ty * S.T[1]) + S.T[1] * (cz - tz * S.T[2]));
       int cls = (A.t_off[0][i] >= R(0.5) ? 1 : 0) | (A.t_off[1][i] >= R(0.5) ? 2 : 0);
       if (dims == 3) cls |= A.t_off[2][i] >= R(0.5) ? 4 : 0;
-      rank = atomicAdd(&cnt[cls * TILE_CELLS_MAX + lc], 1);  // (class-major: lanes of a class hit consecutive banks)
+      rank = atomicAdd(&cnt[cls * TILE_CELLS_MAX + cell], 1);
+      lc = ord[cell];  // from here on cells are named by their in-bin rank
       b = cls * rb + min(rank, rb - 1);
       if (rank >= rb - 1) atomicAdd(&binc[b], 1);  // the last bucket's count (others: popcounts)
       scratch[i] = b * TILE_CELLS_MAX + lc;
@@ -352,6 +394,26 @@ __global__ void k_fill_int(int* a, long n, int v) {
     a[i] = v;
 }
 
+template <int DIMS, int ORDER, typename R>
+static void region_strides_t(SortParams& S) {
+  using G = Geo<DIMS, ORDER, R>;
+  S.rs1 = G::ex;
+  S.rs2 = DIMS == 3 ? G::ex * G::ex : 0;
+  S.rmod = sizeof(R) == 4 ? 32 : 16;
+}
+
+template <typename R>
+static void region_strides(int dims, int order, SortParams& S) {
+#define PIC_RS(DD, OO) \
+  if (dims == DD && order == OO) return region_strides_t<DD, OO, R>(S);
+  PIC_RS(2, 1) PIC_RS(2, 2) PIC_RS(2, 3) PIC_RS(2, 4)
+  PIC_RS(3, 1) PIC_RS(3, 2) PIC_RS(3, 3) PIC_RS(3, 4)
+#undef PIC_RS
+  S.rs1 = 1;
+  S.rs2 = 1;
+  S.rmod = 32;
+}
+
 template <typename R>
 static int launch_sort_t(const pic_ctx* ctx, const pic_particles* p, void* ws, hipStream_t s) {
   SortParams S;
@@ -366,6 +428,7 @@ static int launch_sort_t(const pic_ctx* ctx, const pic_particles* p, void* ws, h
     S.ntile[d] = ctx->ntile[d];
   }
   S.ntiles = ctx->ntiles;
+  region_strides<R>(c.dims, c.order, S);
   S.dn0.init((uint32_t)S.n[0]);
   S.dn1.init((uint32_t)S.n[1]);
   const int ncell = S.n[0] * S.n[1] * S.n[2];
@@ -407,7 +470,9 @@ static int launch_sort_t(const pic_ctx* ctx, const pic_particles* p, void* ws, h
   A.t_cell = (int*)(w + L.tmp_cell);
   A.t_id = (int*)(w + L.tmp_id);
   k_sort_scatter<R><<<dim3(grid), dim3(256), 0, s>>>(A, np, ncell, c.dims, keys, counts, flg);
-  k_sort_place<R><<<dim3((unsigned)S.ntiles), dim3(PLACE_NT), 0, s>>>(A, S, starts, keys, c.dims);
+  int* order = (int*)(w + L.order);
+  k_sort_order<<<dim3(1), dim3(ORDER_NT), 0, s>>>(S, order);
+  k_sort_place<R><<<dim3((unsigned)S.ntiles), dim3(PLACE_NT), 0, s>>>(A, S, starts, order, keys, c.dims);
   const unsigned g2 = grid < 8192 ? grid : 8192;
   k_sort_copyback_dead<R><<<dim3(g2), dim3(256), 0, s>>>(A, starts + S.ntiles, np, c.dims);
   return (int)hipGetLastError();

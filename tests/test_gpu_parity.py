@@ -255,6 +255,15 @@ def test_sort_groups_by_tile_class_and_rank_and_keeps_a_permutation():
     # 8 classes x 4 rank buckets, ranks from 3 on share a bucket)
     o = st["off"]
     cls = (o[0] >= 0.5).astype(np.int64) + 2 * (o[1] >= 0.5) + 4 * (o[2] >= 0.5)
+    # in-bin cell order: cells of the 8^3 tile ranked by (k, residue) where the
+    # residue is the cell's base address in the push kernel's LDS field region
+    # (13 x 13 x 13 samples for quadratic shapes) modulo the 32 banks and k
+    # counts the earlier cells with the same residue
+    lx, ly, lz = np.arange(512) % 8, (np.arange(512) // 8) % 8, np.arange(512) // 64
+    res = (lx + 13 * ly + 169 * lz) % 32
+    occ = np.array([np.sum(res[:i] == res[i]) for i in range(512)])
+    order = np.empty(512, dtype=np.int64)
+    order[np.lexsort((res, occ))] = np.arange(512)
     for t in np.unique(key):
         m = key == t
         cells, kt = c[m], cls[m]
@@ -266,10 +275,12 @@ def test_sort_groups_by_tile_class_and_rank_and_keeps_a_permutation():
             seen[(cl, k)] = rank[i] + 1
         for k in np.unique(kt):
             assert np.all(np.diff(np.minimum(rank[kt == k], 3)) >= 0), (t, k)
-            # a bin below the last rank bucket holds each cell once, in cell order
+            # a bin below the last rank bucket holds each cell once, ordered
+            # by the bank-balanced cell rank
             for r in range(3):
                 cb = cells[(kt == k) & (rank == r)]
-                assert np.all(np.diff(cb) > 0), (t, k, r)
+                lcell = (cb % 40) % T + T * (((cb // 40) % 24) % T + T * ((cb // 960) % T))
+                assert np.all(np.diff(order[lcell]) > 0), (t, k, r)
 
 
 def test_empty_and_ragged_particle_counts():
