@@ -245,6 +245,33 @@ __device__ __forceinline__ void copy_back(const SortArrays<R>& A, long i, long j
   if (A.id) const_cast<int*>(A.id)[j] = idv;
 }
 
+// One particle's payload in registers (for batched copies: all loads of a
+// batch are in flight together).
+template <typename R>
+struct PVal {
+  int cl, id;
+  R o[3], u[3], q;
+  __device__ __forceinline__ void load(const SortArrays<R>& A, long i, int dims) {
+    cl = A.t_cell[i];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) o[d] = d < dims ? A.t_off[d][i] : R(0);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) u[c] = A.t_u[c][i];
+    q = A.q ? A.t_q[i] : R(0);
+    id = A.id ? A.t_id[i] : 0;
+  }
+  __device__ __forceinline__ void store(const SortArrays<R>& A, long j, int dims) const {
+    const_cast<int*>(A.cell)[j] = cl;
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+      if (d < dims) const_cast<R*>(A.off[d])[j] = o[d];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) const_cast<R*>(A.u[c])[j] = u[c];
+    if (A.q) const_cast<R*>(A.q)[j] = q;
+    if (A.id) const_cast<int*>(A.id)[j] = id;
+  }
+};
+
 // Copy back of the dead bin (absorbed particles, in scatter order).
 template <typename R>
 __global__ void k_sort_copyback_dead(SortArrays<R> A, const int* __restrict__ dead_start, long np,
@@ -266,19 +293,20 @@ __global__ void k_sort_copyback_dead(SortArrays<R> A, const int* __restrict__ de
 constexpr int ORDER_NT = 512;
 __global__ void __launch_bounds__(ORDER_NT) k_sort_order(SortParams S, int* __restrict__ order) {
   __shared__ int cnt[32];
+  __shared__ int res[ORDER_NT];
   const int ncells = S.T[0] * S.T[1] * S.T[2];
   const int lc = threadIdx.x;
   if (lc < 32) cnt[lc] = 0;
-  __syncthreads();
-  auto residue = [&](int c) {
-    const int lx = c % S.T[0], ly = (c / S.T[0]) % S.T[1], lz = c / (S.T[0] * S.T[1]);
-    return (lx + S.rs1 * ly + S.rs2 * lz) % S.rmod;
-  };
   int r = 0, k = 0;
   if (lc < ncells) {
-    r = residue(lc);
+    const int lx = lc % S.T[0], ly = (lc / S.T[0]) % S.T[1], lz = lc / (S.T[0] * S.T[1]);
+    r = (lx + S.rs1 * ly + S.rs2 * lz) % S.rmod;
+    res[lc] = r;
+  }
+  __syncthreads();
+  if (lc < ncells) {
     atomicAdd(&cnt[r], 1);
-    for (int c = 0; c < lc; ++c) k += residue(c) == r;
+    for (int c = 0; c < lc; ++c) k += res[c] == r;
   }
   __syncthreads();
   if (lc < ncells) {
@@ -296,7 +324,7 @@ __global__ void __launch_bounds__(ORDER_NT) k_sort_order(SortParams S, int* __re
 // class's last rank bucket every cell appears once, so the k-th cell of the
 // bin (in cell order, from a bit mask of the bin's cells) takes slot k; the
 // last bucket is filled in arrival order.
-constexpr int PLACE_NT = 1024;
+constexpr int PLACE_NT = 512;
 constexpr int TILE_CELLS_MAX = 512;
 template <typename R>
 __global__ void __launch_bounds__(PLACE_NT) k_sort_place(SortArrays<R> A, SortParams S,
@@ -322,42 +350,62 @@ __global__ void __launch_bounds__(PLACE_NT) k_sort_place(SortArrays<R> A, SortPa
   const int rb = NB >> dims;  // rank buckets per class
   // (wavefront-uniform loop: the mask update below shuffles across lanes)
   const int lane = threadIdx.x & 63;
-  for (int i = beg + threadIdx.x; i - lane < end; i += PLACE_NT) {
-    const bool in = i < end;
-    int b = 0, lc = 0, rank = 0;
-    if (in) {
-      const int cl = A.t_cell[i];
-      const uint32_t rest = S.dn0.div((uint32_t)cl);
-      const int cx = cl - (int)rest * S.n[0];
-      int cy = (int)rest, cz = 0;
-      if (dims == 3) {
-        const uint32_t r2 = S.dn1.div(rest);
-        cy = (int)(rest - r2 * S.n[1]);
-        cz = (int)r2;
+  constexpr int PB1 = 4;
+  for (int i0 = beg + threadIdx.x; i0 - lane < end; i0 += PB1 * PLACE_NT) {
+    int pc[PB1];
+    R po[PB1][3];
+#pragma unroll
+    for (int k = 0; k < PB1; ++k) {  // the batch's loads, all in flight together
+      const int i = i0 + k * PLACE_NT;
+      pc[k] = 0;
+      po[k][0] = po[k][1] = po[k][2] = R(0);
+      if (i < end) {
+        pc[k] = A.t_cell[i];
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+          if (d < dims) po[k][d] = A.t_off[d][i];
       }
-      const int cell = (cx - tx * S.T[0]) + S.T[0] * ((cy - ty * S.T[1]) + S.T[1] * (cz - tz * S.T[2]));
-      int cls = (A.t_off[0][i] >= R(0.5) ? 1 : 0) | (A.t_off[1][i] >= R(0.5) ? 2 : 0);
-      if (dims == 3) cls |= A.t_off[2][i] >= R(0.5) ? 4 : 0;
-      rank = atomicAdd(&cnt[cls * TILE_CELLS_MAX + cell], 1);
-      lc = ord[cell];  // from here on cells are named by their in-bin rank
-      b = cls * rb + min(rank, rb - 1);
-      if (rank >= rb - 1) atomicAdd(&binc[b], 1);  // the last bucket's count (others: popcounts)
-      scratch[i] = b * TILE_CELLS_MAX + lc;
     }
-    // mask bits of the bins below the last bucket, OR-ed over runs of lanes
-    // that share a mask word (neighbouring cells of one bin): one LDS atomic
-    // per run instead of one per lane on the same word
-    const bool mk = in && rank < rb - 1;
-    const int word = mk ? b * W + (lc >> 5) : -1 - lane;
-    int head, len;
-    wave_runs(word, head, len);
-    unsigned bits = mk ? 1u << (lc & 31) : 0u;
-    for (int off = 1; off < 64; off <<= 1) {
-      const unsigned v = __shfl_up(bits, off, 64);
-      if (lane - off >= head) bits |= v;
+#pragma unroll
+    for (int k = 0; k < PB1; ++k) {
+      const int i = i0 + k * PLACE_NT;
+      const bool in = i < end;
+      int b = 0, lc = 0, rank = 0;
+      if (in) {
+        const int cl = pc[k];
+        const uint32_t rest = S.dn0.div((uint32_t)cl);
+        const int cx = cl - (int)rest * S.n[0];
+        int cy = (int)rest, cz = 0;
+        if (dims == 3) {
+          const uint32_t r2 = S.dn1.div(rest);
+          cy = (int)(rest - r2 * S.n[1]);
+          cz = (int)r2;
+        }
+        const int cell =
+            (cx - tx * S.T[0]) + S.T[0] * ((cy - ty * S.T[1]) + S.T[1] * (cz - tz * S.T[2]));
+        int cls = (po[k][0] >= R(0.5) ? 1 : 0) | (po[k][1] >= R(0.5) ? 2 : 0);
+        if (dims == 3) cls |= po[k][2] >= R(0.5) ? 4 : 0;
+        rank = atomicAdd(&cnt[cls * TILE_CELLS_MAX + cell], 1);
+        lc = ord[cell];  // from here on cells are named by their in-bin rank
+        b = cls * rb + min(rank, rb - 1);
+        if (rank >= rb - 1) atomicAdd(&binc[b], 1);  // the last bucket's count (others: popcounts)
+        scratch[i] = b * TILE_CELLS_MAX + lc;
+      }
+      // mask bits of the bins below the last bucket, OR-ed over runs of lanes
+      // that share a mask word (neighbouring cells of one bin): one LDS atomic
+      // per run instead of one per lane on the same word
+      const bool mk = in && rank < rb - 1;
+      const int word = mk ? b * W + (lc >> 5) : -1 - lane;
+      int head, len;
+      wave_runs(word, head, len);
+      unsigned bits = mk ? 1u << (lc & 31) : 0u;
+      for (int off = 1; off < 64; off <<= 1) {
+        const unsigned v = __shfl_up(bits, off, 64);
+        if (lane - off >= head) bits |= v;
+      }
+      bits = __shfl(bits, head + len - 1, 64);
+      if (mk && lane == head) atomicOr(&(&mask[0][0])[word], bits);
     }
-    bits = __shfl(bits, head + len - 1, 64);
-    if (mk && lane == head) atomicOr(&(&mask[0][0])[word], bits);
   }
   __syncthreads();
   if (threadIdx.x < NB) {
@@ -377,15 +425,32 @@ __global__ void __launch_bounds__(PLACE_NT) k_sort_place(SortArrays<R> A, SortPa
     }
   }
   __syncthreads();
-  for (int i = beg + threadIdx.x; i < end; i += PLACE_NT) {
-    const int v = __builtin_nontemporal_load(&scratch[i]);
-    const int b = v / TILE_CELLS_MAX, lc = v % TILE_CELLS_MAX;
-    int j;
-    if (b % rb < rb - 1)
-      j = bin0[b] + pre[b][lc >> 5] + __popc(mask[b][lc >> 5] & ((1u << (lc & 31)) - 1u));
-    else
-      j = atomicAdd(&bin0[b], 1);  // last bucket (no mask): arrival order
-    copy_back(A, i, j, dims);
+  // batches of PB particles per thread: every load of a batch first, then
+  // the slots, then every store
+  constexpr int PB = 4;
+  for (int i0 = beg + threadIdx.x; i0 < end; i0 += PB * PLACE_NT) {
+    int v[PB];
+    PVal<R> pv[PB];
+#pragma unroll
+    for (int k = 0; k < PB; ++k) {
+      const int i = i0 + k * PLACE_NT;
+      if (i < end) {
+        v[k] = scratch[i];
+        pv[k].load(A, i, dims);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < PB; ++k) {
+      if (i0 + k * PLACE_NT < end) {
+        const int b = v[k] / TILE_CELLS_MAX, lc = v[k] % TILE_CELLS_MAX;
+        int j;
+        if (b % rb < rb - 1)
+          j = bin0[b] + pre[b][lc >> 5] + __popc(mask[b][lc >> 5] & ((1u << (lc & 31)) - 1u));
+        else
+          j = atomicAdd(&bin0[b], 1);  // last bucket (no mask): arrival order
+        pv[k].store(A, j, dims);
+      }
+    }
   }
 }
 
