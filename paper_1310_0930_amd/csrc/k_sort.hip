@@ -85,16 +85,43 @@ __device__ __forceinline__ long spread_block(unsigned b, unsigned n) {
 }
 
 // Tile key of every particle (ntiles: dead) and the histogram of the keys.
-__global__ void k_sort_count(SortParams S, const int* __restrict__ cell, long np, int ncell,
-                             int* __restrict__ keys, int* __restrict__ counts, DevFlags* flg) {
-  const long p = spread_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-  if (p == 0) flg->qmax = 0u;  // the scatter (next launch) takes the new maximum
+// A workgroup takes COUNT_PER consecutive particles (chunks spread as
+// above); runs of the chunk's first key, which after a sort is the tile of
+// nearly the whole chunk, are summed in LDS and added with one global
+// atomic, other runs add their own.
+constexpr int COUNT_NT = 256, COUNT_PER = 8;
+__global__ void __launch_bounds__(COUNT_NT) k_sort_count(SortParams S, const int* __restrict__ cell,
+                                                         long np, int ncell, int* __restrict__ keys,
+                                                         int* __restrict__ counts, DevFlags* flg) {
+  __shared__ int acc;
+  const long c0 = spread_block(blockIdx.x, gridDim.x) * (long)(COUNT_NT * COUNT_PER);
+  if (c0 == 0 && threadIdx.x == 0) flg->qmax = 0u;  // the scatter takes the new maximum
   const int lane = threadIdx.x & 63;
-  const int key = p < np ? tile_key(S, cell[p], ncell) : -1;
-  if (p < np) keys[p] = key;
-  int head, len;
-  wave_runs(key, head, len);
-  if (lane == head && key >= 0) atomicAdd(&counts[key], len);
+  const int key0 = c0 < np ? tile_key(S, cell[c0], ncell) : -1;
+  if (threadIdx.x == 0) acc = 0;
+  __syncthreads();
+  int mine = 0;  // this thread's run lengths of key0
+#pragma unroll
+  for (int k = 0; k < COUNT_PER; ++k) {
+    const long p = c0 + k * COUNT_NT + threadIdx.x;
+    const int key = p < np ? tile_key(S, cell[p], ncell) : -1;
+    if (p < np) keys[p] = key;
+    if (__ballot(key == key0) == ~0ull) {  // the whole wavefront in key0's tile (the usual case)
+      if (lane == 0) mine += 64;
+      continue;
+    }
+    int head, len;
+    wave_runs(key, head, len);
+    if (lane == head && key >= 0) {
+      if (key == key0)
+        mine += len;
+      else
+        atomicAdd(&counts[key], len);
+    }
+  }
+  if (mine) atomicAdd(&acc, mine);
+  __syncthreads();
+  if (threadIdx.x == 0 && acc) atomicAdd(&counts[key0], acc);
 }
 
 // Exclusive scan of counts[0..nb) in three passes: per-block sums, a scan of
@@ -192,8 +219,9 @@ __global__ void k_sort_scatter(SortArrays<R> A, long np, int ncell, int dims,
     if (A.q) qv = A.q[p];
     if (A.id) idv = A.id[p];
   }
-  int head, len;
-  wave_runs(key, head, len);
+  int head = 0, len = 64;
+  if (__ballot(key == __builtin_amdgcn_readfirstlane(key)) != ~0ull)  // else one run (usual)
+    wave_runs(key, head, len);
   const int lane = threadIdx.x & 63;
   int base = 0;
   if (lane == head && key >= 0) base = atomicAdd(&cursor[key], len);
@@ -515,7 +543,9 @@ static int launch_sort_t(const pic_ctx* ctx, const pic_particles* p, void* ws, h
   k_fill_int<<<fill_grid(nb), dim3(256), 0, s>>>(counts, nb, 0);
   const unsigned grid = (unsigned)((np + 255) / 256);
   DevFlags* flg = (DevFlags*)(w + L.flags);
-  k_sort_count<<<dim3(grid), dim3(256), 0, s>>>(S, p->cell, np, ncell, keys, counts, flg);
+  const long cchunk = (long)COUNT_NT * COUNT_PER;
+  k_sort_count<<<dim3((unsigned)((np + cchunk - 1) / cchunk)), dim3(COUNT_NT), 0, s>>>(
+      S, p->cell, np, ncell, keys, counts, flg);
   k_scan_sums<<<dim3(nblk), dim3(SCAN_B), 0, s>>>(counts, nb, bsum);
   k_scan_blocks<<<dim3(1), dim3(SCAN_B), 0, s>>>(bsum, nblk);
   k_scan_apply<<<dim3(nblk), dim3(SCAN_B), 0, s>>>(counts, nb, bsum, bstart);
