@@ -228,45 +228,60 @@ def test_fdtd_eigenmode_fp64():
 
 
 # ---------------------------------------------------------------- edge cases
-def test_sort_groups_by_tile_class_and_rank_and_keeps_a_permutation():
-    w = I.Workload("w3d_sort", 3, (40, 24, 16), (0.2, 0.2, 0.2), 2, 3, 0.3, 1,
-                   seed=I.SEED_BASE + 70)
-    pl, E, B = inputs_for(w)
-    rng = np.random.default_rng(5)
-    perm = rng.permutation(pl.np)
-    pl = I.Plasma(pl.cell[perm].copy(), pl.off[:, perm].copy(), pl.u[:, perm].copy(), None,
-                  pl.q_const)
-    sim = gpu_sim(w, 4, pl, E, B)
-    sim.sort()
-    st = sim.download()
+def _tile_geometry(dims, order, rb):
+    """Tile sizes and the push kernel's LDS field-region strides for a
+    configuration (the tile-kernel geometry), and the number of distinct bank
+    positions of a field sample (32 four-byte banks)."""
+    wide = order == 4 or (rb == 8 and order == 3)
+    if dims == 2:
+        T, TZ, A = 16, 1, 2
+    else:
+        T = 4 if (order == 4 and rb == 8) else 8
+        TZ, A = (4 if wide else T), 1
+    g_lo = -2 if order >= 3 else -1
+    g_hi = 1 if order == 1 else (3 if order == 4 else 2)
+    ex = T + 2 * A + g_hi - g_lo
+    return T, TZ, ex, (ex * ex if dims == 3 else 0), (32 if rb == 4 else 16)
+
+
+def _check_sorted(w, rb, pl, st):
     ids = st["id"]
     assert np.array_equal(np.sort(ids), np.arange(pl.np))
     # the payload moved with its particle
     assert np.array_equal(st["cell"], pl.cell[ids])
     np.testing.assert_array_equal(st["off"], pl.off[:, ids].astype(np.float64))
+    np.testing.assert_array_equal(st["u"], pl.u[:, ids].astype(np.float64))
+    D = w.dims
+    n0, n1, _ = w.n3
+    T, TZ, ex, plane, rmod = _tile_geometry(D, w.order, rb)
     c = st["cell"]
-    T = 8
-    tx, ty, tz = (c % 40) // T, (c // 40) % 24 // T, c // (40 * 24) // T
-    key = tx + 5 * (ty + 3 * tz)
+    cx, cy, cz = c % n0, (c // n0) % n1, c // (n0 * n1)
+    nt0, nt1 = -(-n0 // T), -(-n1 // T)
+    key = cx // T + nt0 * (cy // T + nt1 * (cz // TZ))
     assert np.all(np.diff(key) >= 0)
     # inside a tile the particles come class by class (class bit d: offset
     # along d >= 1/2), and within a class rank by rank: the k-th particle of
     # every cell in that class before any (k+1)-th one (32 bins per tile:
-    # 8 classes x 4 rank buckets, ranks from 3 on share a bucket)
+    # 2^D classes x 32 / 2^D rank buckets, the last bucket shared by the
+    # higher ranks)
     o = st["off"]
-    cls = (o[0] >= 0.5).astype(np.int64) + 2 * (o[1] >= 0.5) + 4 * (o[2] >= 0.5)
-    # in-bin cell order: cells of the 8^3 tile ranked by (k, residue) where the
-    # residue is the cell's base address in the push kernel's LDS field region
-    # (13 x 13 x 13 samples for quadratic shapes) modulo the 32 banks and k
-    # counts the earlier cells with the same residue
-    lx, ly, lz = np.arange(512) % 8, (np.arange(512) // 8) % 8, np.arange(512) // 64
-    res = (lx + 13 * ly + 169 * lz) % 32
-    occ = np.array([np.sum(res[:i] == res[i]) for i in range(512)])
-    order = np.empty(512, dtype=np.int64)
-    order[np.lexsort((res, occ))] = np.arange(512)
+    cls = sum((o[d] >= 0.5).astype(np.int64) << d for d in range(D))
+    rbk = 32 >> D
+    # in-bin cell order: the tile's cells ranked by (k, residue), the residue
+    # being the cell's base address in the push kernel's LDS field region
+    # modulo the bank positions and k counting the earlier cells with the
+    # same residue
+    nc = T * T * TZ
+    lc_all = np.arange(nc)
+    res = (lc_all % T + ex * ((lc_all // T) % T) + plane * (lc_all // (T * T))) % rmod
+    occ = np.array([np.sum(res[:i] == res[i]) for i in range(nc)])
+    order = np.empty(nc, dtype=np.int64)
+    order[np.lexsort((res, occ))] = np.arange(nc)
+    lcell = (cx % T) + T * ((cy % T) + T * (cz % TZ))
+    nlast = 0
     for t in np.unique(key):
         m = key == t
-        cells, kt = c[m], cls[m]
+        cells, kt, lt = c[m], cls[m], lcell[m]
         assert np.all(np.diff(kt) >= 0), t
         seen = {}
         rank = np.empty(cells.size, dtype=np.int64)
@@ -274,13 +289,37 @@ def test_sort_groups_by_tile_class_and_rank_and_keeps_a_permutation():
             rank[i] = seen.get((cl, k), 0)
             seen[(cl, k)] = rank[i] + 1
         for k in np.unique(kt):
-            assert np.all(np.diff(np.minimum(rank[kt == k], 3)) >= 0), (t, k)
+            assert np.all(np.diff(np.minimum(rank[kt == k], rbk - 1)) >= 0), (t, k)
             # a bin below the last rank bucket holds each cell once, ordered
             # by the bank-balanced cell rank
-            for r in range(3):
-                cb = cells[(kt == k) & (rank == r)]
-                lcell = (cb % 40) % T + T * (((cb // 40) % 24) % T + T * ((cb // 960) % T))
-                assert np.all(np.diff(order[lcell]) > 0), (t, k, r)
+            for r in range(rbk - 1):
+                assert np.all(np.diff(order[lt[(kt == k) & (rank == r)]]) > 0), (t, k, r)
+        nlast += int(np.sum(rank >= rbk - 1))
+    return nlast
+
+
+@pytest.mark.parametrize("dims,order,rb,ppc", [(3, 2, 4, 3), (3, 2, 8, 3), (3, 3, 4, 3),
+                                               (3, 4, 8, 3), (2, 2, 4, 6), (3, 1, 4, 60)])
+def test_sort_groups_by_tile_class_and_rank_and_keeps_a_permutation(dims, order, rb, ppc):
+    """The tile sort on a shuffled ragged grid: a permutation that carries the
+    payload, tiles in order, and inside a tile the (class, rank, cell order)
+    placement; ppc = 60 puts many particles in the last rank bucket."""
+    n = (40, 24, 16) if dims == 3 else (72, 40)
+    if ppc > 10:
+        n = (20, 12, 9)
+    w = I.Workload("w_sort", dims, n, (0.2,) * dims, order, ppc, 0.3, 1,
+                   seed=I.SEED_BASE + 70 + order + 10 * dims + rb)
+    pl, E, B = inputs_for(w)
+    rng = np.random.default_rng(5)
+    perm = rng.permutation(pl.np)
+    pl = I.Plasma(pl.cell[perm].copy(), pl.off[:, perm].copy(), pl.u[:, perm].copy(), None,
+                  pl.q_const)
+    sim = gpu_sim(w, rb, pl, E, B)
+    sim.sort()
+    nlast = _check_sorted(w, rb, pl, sim.download())
+    say("sort", dims, order, rb, ppc, "np", pl.np, "last-bucket particles", nlast)
+    if ppc > 10:
+        assert nlast > pl.np // 4
 
 
 def test_empty_and_ragged_particle_counts():
