@@ -366,24 +366,29 @@ __global__ void __launch_bounds__(PLACE_NT) k_sort_place(SortArrays<R> A, SortPa
   __shared__ int binc[NB];
   __shared__ int bin0[NB];
   __shared__ int ord[TILE_CELLS_MAX];
+  __shared__ int inv[TILE_CELLS_MAX];
   const int t = blockIdx.x;
   const int beg = tstart[t], end = tstart[t + 1];
   if (beg == end) return;
-  for (int i = threadIdx.x; i < TILE_CELLS_MAX; i += PLACE_NT) ord[i] = order[i];
+  const int ncells = S.T[0] * S.T[1] * S.T[2];
+  for (int i = threadIdx.x; i < ncells; i += PLACE_NT) {
+    const int o = order[i];
+    ord[i] = o;
+    inv[o] = i;
+  }
   for (int i = threadIdx.x; i < TILE_CELLS_MAX * 8; i += PLACE_NT) cnt[i] = 0;
-  for (int i = threadIdx.x; i < NB * W; i += PLACE_NT) (&mask[0][0])[i] = 0u;
   for (int i = threadIdx.x; i < NB; i += PLACE_NT) binc[i] = 0;
   __syncthreads();
   const int tx = t % S.ntile[0], ty = (t / S.ntile[0]) % S.ntile[1], tz = t / (S.ntile[0] * S.ntile[1]);
   const int rb = NB >> dims;  // rank buckets per class
-  // (wavefront-uniform loop: the mask update below shuffles across lanes)
-  const int lane = threadIdx.x & 63;
+  // pass 1: class and rank of every particle (batches of PB1 per thread,
+  // all loads of a batch in flight together)
   constexpr int PB1 = 4;
-  for (int i0 = beg + threadIdx.x; i0 - lane < end; i0 += PB1 * PLACE_NT) {
+  for (int i0 = beg + threadIdx.x; i0 < end; i0 += PB1 * PLACE_NT) {
     int pc[PB1];
     R po[PB1][3];
 #pragma unroll
-    for (int k = 0; k < PB1; ++k) {  // the batch's loads, all in flight together
+    for (int k = 0; k < PB1; ++k) {
       const int i = i0 + k * PLACE_NT;
       pc[k] = 0;
       po[k][0] = po[k][1] = po[k][2] = R(0);
@@ -397,9 +402,7 @@ __global__ void __launch_bounds__(PLACE_NT) k_sort_place(SortArrays<R> A, SortPa
 #pragma unroll
     for (int k = 0; k < PB1; ++k) {
       const int i = i0 + k * PLACE_NT;
-      const bool in = i < end;
-      int b = 0, lc = 0, rank = 0;
-      if (in) {
+      if (i < end) {
         const int cl = pc[k];
         const uint32_t rest = S.dn0.div((uint32_t)cl);
         const int cx = cl - (int)rest * S.n[0];
@@ -413,34 +416,43 @@ __global__ void __launch_bounds__(PLACE_NT) k_sort_place(SortArrays<R> A, SortPa
             (cx - tx * S.T[0]) + S.T[0] * ((cy - ty * S.T[1]) + S.T[1] * (cz - tz * S.T[2]));
         int cls = (po[k][0] >= R(0.5) ? 1 : 0) | (po[k][1] >= R(0.5) ? 2 : 0);
         if (dims == 3) cls |= po[k][2] >= R(0.5) ? 4 : 0;
-        rank = atomicAdd(&cnt[cls * TILE_CELLS_MAX + cell], 1);
-        lc = ord[cell];  // from here on cells are named by their in-bin rank
-        b = cls * rb + min(rank, rb - 1);
-        if (rank >= rb - 1) atomicAdd(&binc[b], 1);  // the last bucket's count (others: popcounts)
-        scratch[i] = b * TILE_CELLS_MAX + lc;
+        const int rank = atomicAdd(&cnt[cls * TILE_CELLS_MAX + cell], 1);
+        // from here on a cell is named by its rank in the in-bin order
+        scratch[i] = (cls * rb + min(rank, rb - 1)) * TILE_CELLS_MAX + ord[cell];
       }
-      // mask bits of the bins below the last bucket, OR-ed over runs of lanes
-      // that share a mask word (neighbouring cells of one bin): one LDS atomic
-      // per run instead of one per lane on the same word
-      const bool mk = in && rank < rb - 1;
-      const int word = mk ? b * W + (lc >> 5) : -1 - lane;
-      int head, len;
-      wave_runs(word, head, len);
-      unsigned bits = mk ? 1u << (lc & 31) : 0u;
-      for (int off = 1; off < 64; off <<= 1) {
-        const unsigned v = __shfl_up(bits, off, 64);
-        if (lane - off >= head) bits |= v;
-      }
-      bits = __shfl(bits, head + len - 1, 64);
-      if (mk && lane == head) atomicOr(&(&mask[0][0])[word], bits);
     }
+  }
+  __syncthreads();
+  // bin masks from the counts: bin (class, r < last) holds cell c iff c has
+  // more than r particles of that class; one thread per (class, mask word),
+  // which also counts the class's last bucket
+  if (threadIdx.x < (1 << dims) * W) {
+    const int cls = threadIdx.x / W, w = threadIdx.x % W;
+    constexpr int MR = NB / 4 - 1;  // rb - 1 <= MR masks (rb = NB / 2^dims, dims >= 2)
+    unsigned m[MR];
+#pragma unroll
+    for (int r = 0; r < MR; ++r) m[r] = 0u;
+    int last = 0;
+    for (int bit = 0; bit < 32; ++bit) {
+      const int lcr = w * 32 + bit;
+      if (lcr >= ncells) break;
+      const int n = cnt[cls * TILE_CELLS_MAX + inv[lcr]];
+#pragma unroll
+      for (int r = 0; r < MR; ++r)
+        if (r < rb - 1 && n > r) m[r] |= 1u << bit;
+      last += max(0, n - (rb - 1));
+    }
+#pragma unroll
+    for (int r = 0; r < MR; ++r)
+      if (r < rb - 1) mask[cls * rb + r][w] = m[r];
+    if (last) atomicAdd(&binc[cls * rb + rb - 1], last);
   }
   __syncthreads();
   if (threadIdx.x < NB) {
     int acc = 0;
     for (int w = 0; w < W; ++w) {
       pre[threadIdx.x][w] = acc;
-      acc += __popc(mask[threadIdx.x][w]);
+      acc += __popc(threadIdx.x % rb < rb - 1 ? mask[threadIdx.x][w] : 0u);
     }
     if (threadIdx.x % rb < rb - 1) binc[threadIdx.x] = acc;
   }
