@@ -237,7 +237,11 @@ __global__ void k_sort_scatter(SortArrays<R> A, long np, int ncell, int dims,
       m = __float_as_uint(f);
     }
     for (int sh = 32; sh > 0; sh >>= 1) m = max(m, (unsigned)__shfl_xor((int)m, sh, 64));
-    if (lane == 0) atomicMax(&flg->qmax, m);
+    // every wavefront's atomic on the one word would serialize: skip it when
+    // the maximum so far (a possibly stale read, which can only cost an
+    // extra atomic) already covers this wavefront's
+    if (lane == 0 && m > __hip_atomic_load(&flg->qmax, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+      atomicMax(&flg->qmax, m);
   }
   if (!in) return;
   const long dst = (long)base + (lane - head);

@@ -136,9 +136,11 @@ WORKLOADS = {
     "w3d_128_quadratic": Workload("w3d_128_quadratic", 3, (128, 128, 128), (0.2, 0.2, 0.2), 2, 8,
                                   0.05, 50, seed=SEED_BASE + 2),
     # 3D 256x128x128 cubic, cold plasma with a 20-cell ramp, a0=4 laser, open y,z
+    # (sorted every 4 steps: electrons in the a0 = 4 pulse move 0.4 cells per
+    # step along x and leave their tile's one-cell drift allowance quickly)
     "w3d_256_cubic_laser": Workload("w3d_256_cubic_laser", 3, (256, 128, 128), (0.1, 0.2, 0.2), 3,
                                     8, 0.0, 200, bc=(PERIODIC, OPEN, OPEN), ramp_cells=20.0,
-                                    laser=Laser(), seed=SEED_BASE + 3),
+                                    laser=Laser(), sort_every=4, seed=SEED_BASE + 3),
     # 2D3V 512x256 quadratic, 16 ppc, ramp + laser, open y (adjoint workload)
     "w2d_512_quadratic_laser": Workload("w2d_512_quadratic_laser", 2, (512, 256), (0.1, 0.2), 2, 16,
                                         0.0, 50, bc=(PERIODIC, OPEN), ramp_cells=20.0,
@@ -146,7 +148,7 @@ WORKLOADS = {
     # 3D 512x256x256 quadratic, cold uniform plasma + laser, periodic, sort every 20
     "w3d_512_quadratic_laser": Workload("w3d_512_quadratic_laser", 3, (512, 256, 256),
                                         (0.1, 0.2, 0.2), 2, 8, 0.0, 100, laser=Laser(),
-                                        sort_every=20, seed=SEED_BASE + 5),
+                                        sort_every=10, seed=SEED_BASE + 5),
 }
 # The 128^3 warm-plasma recipe at the other orders of Table 3 (linear, cubic,
 # quartic), and with a mobile ion species (hydrogen mass ratio, thermal
