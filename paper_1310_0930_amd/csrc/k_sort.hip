@@ -357,6 +357,7 @@ __global__ void __launch_bounds__(ORDER_NT) k_sort_order(SortParams S, int* __re
 // bin (in cell order, from a bit mask of the bin's cells) takes slot k; the
 // last bucket is filled in arrival order.
 constexpr int PLACE_NT = 512;
+constexpr int PLACE_SRC_MAX = 8192;
 constexpr int TILE_CELLS_MAX = 512;
 template <typename R>
 __global__ void __launch_bounds__(PLACE_NT) k_sort_place(SortArrays<R> A, SortParams S,
@@ -371,6 +372,7 @@ __global__ void __launch_bounds__(PLACE_NT) k_sort_place(SortArrays<R> A, SortPa
   __shared__ int bin0[NB];
   __shared__ int ord[TILE_CELLS_MAX];
   __shared__ int inv[TILE_CELLS_MAX];
+  __shared__ int src[PLACE_SRC_MAX];  // source of each slot of the tile
   const int t = blockIdx.x;
   const int beg = tstart[t], end = tstart[t + 1];
   if (beg == end) return;
@@ -469,32 +471,40 @@ __global__ void __launch_bounds__(PLACE_NT) k_sort_place(SortArrays<R> A, SortPa
     }
   }
   __syncthreads();
-  // batches of PB particles per thread: every load of a batch first, then
-  // the slots, then every store
+  // Slots.  Stores to scattered slots cost more than loads from them (each
+  // partial cache-line write is merged in memory), so when the tile fits,
+  // pass 2 records the source of every slot in LDS and pass 3 copies slot by
+  // slot (gathered loads, coalesced stores); a larger tile stores directly.
+  const int n = end - beg;
+  const bool staged = n <= PLACE_SRC_MAX;
+  for (int i = beg + threadIdx.x; i < end; i += PLACE_NT) {
+    const int v = scratch[i];
+    const int b = v / TILE_CELLS_MAX, lc = v % TILE_CELLS_MAX;
+    int j;
+    if (b % rb < rb - 1)
+      j = bin0[b] + pre[b][lc >> 5] + __popc(mask[b][lc >> 5] & ((1u << (lc & 31)) - 1u));
+    else
+      j = atomicAdd(&bin0[b], 1);  // last bucket (no mask): arrival order
+    if (staged) {
+      src[j - beg] = i;
+    } else {
+      PVal<R> pv;
+      pv.load(A, i, dims);
+      pv.store(A, j, dims);
+    }
+  }
+  if (!staged) return;
+  __syncthreads();
+  // pass 3: batches of PB slots per thread, every load of a batch first
   constexpr int PB = 4;
-  for (int i0 = beg + threadIdx.x; i0 < end; i0 += PB * PLACE_NT) {
-    int v[PB];
+  for (int t0 = threadIdx.x; t0 < n; t0 += PB * PLACE_NT) {
     PVal<R> pv[PB];
 #pragma unroll
-    for (int k = 0; k < PB; ++k) {
-      const int i = i0 + k * PLACE_NT;
-      if (i < end) {
-        v[k] = scratch[i];
-        pv[k].load(A, i, dims);
-      }
-    }
+    for (int k = 0; k < PB; ++k)
+      if (t0 + k * PLACE_NT < n) pv[k].load(A, src[t0 + k * PLACE_NT], dims);
 #pragma unroll
-    for (int k = 0; k < PB; ++k) {
-      if (i0 + k * PLACE_NT < end) {
-        const int b = v[k] / TILE_CELLS_MAX, lc = v[k] % TILE_CELLS_MAX;
-        int j;
-        if (b % rb < rb - 1)
-          j = bin0[b] + pre[b][lc >> 5] + __popc(mask[b][lc >> 5] & ((1u << (lc & 31)) - 1u));
-        else
-          j = atomicAdd(&bin0[b], 1);  // last bucket (no mask): arrival order
-        pv[k].store(A, j, dims);
-      }
-    }
+    for (int k = 0; k < PB; ++k)
+      if (t0 + k * PLACE_NT < n) pv[k].store(A, beg + t0 + k * PLACE_NT, dims);
   }
 }
 
