@@ -1,5 +1,6 @@
 // Hand-written adjoint (vector-Jacobian product) of one gather + Boris push +
-// move + split + Esirkepov deposit pass, one thread per particle.
+// move + split + Esirkepov deposit pass: one thread per particle in global
+// memory, or in 2D out of LDS per tile of sorted particles.
 //
 // Given the adjoints of the step's outputs -- lamX^{n+1} (positions, in cell
 // units), lamU^{n+1/2} (momenta) and lamJ^{n+1/2} (the current, produced by
@@ -8,7 +9,7 @@
 // through the charge-conserving deposit (segment end points as functions of
 // the path's ends and of the crossing fractions f = (P - X0)/(X1 - X0)),
 // the move X1 = X0 + dt u/(gamma dx), the Boris rotation and the gather,
-// whose transpose scatters lamE^n, lamB^n with global atomics.  The result
+// whose transpose scatters lamE^n, lamB^n (atomics).  The result
 // overwrites lamX, lamU with their values at step n and adds to lamE, lamB.
 // The map is differentiated along the branch the forward takes (cell and
 // piece choices, crossing structure), where it is smooth.
@@ -57,12 +58,54 @@ __device__ __forceinline__ int sample_index(const KParams<R>& P, int dims, bool 
   return ix + P.n[0] * (iy + P.n[1] * iz);
 }
 
+// Sample access of the adjoint helpers, at lattice coordinates: E^n/B^n
+// (read), lamE/lamB (added to) and lamJ (read).  AdjGlobal goes to the
+// global arrays with the domain's wrap and open faces; AdjLds to a tile's
+// LDS regions (coordinates relative to the tile origin), the lamE/lamB
+// region accumulating in double.
+template <int DIMS, typename R>
+struct AdjGlobal {
+  const KParams<R>& P;
+  const DFields<R>& F;
+  R* const* lamE;
+  R* const* lamB;
+  R* const* lamJ;
+  // adds v to the adjoint of sample (isb, c, x, y, z) and returns the field there
+  __device__ __forceinline__ R field_add(bool isb, int c, int x, int y, int z, R v) const {
+    const int g = sample_index<R>(P, DIMS, isb, c, x, y, z);
+    if (g < 0) return R(0);
+    atomicAdd(&(isb ? lamB : lamE)[c][g], v);
+    return (isb ? F.B : F.E)[c][g];
+  }
+  __device__ __forceinline__ R lamj(int c, int x, int y, int z) const {
+    const int g = sample_index<R>(P, DIMS, false, c, x, y, z);
+    return g < 0 ? R(0) : lamJ[c][g];
+  }
+};
+
+template <int DIMS, int ORDER, typename R>
+struct AdjLds {
+  using G = Geo<DIMS, ORDER, R>;
+  const R* eb;   // E^n (0..2), B^n (3..5) over the field region
+  const R* lj;   // lamJ over the current region
+  double* leb;   // lamE (0..2), lamB (3..5) over the field region
+  __device__ __forceinline__ R field_add(bool isb, int c, int x, int y, int z, R v) const {
+    const int i = (DIMS == 3 ? (z - G::e_lo_z) * G::ex : 0) * G::ex + (y - G::e_lo) * G::ex +
+                  (x - G::e_lo) + (isb ? 3 + c : c) * G::e_vol;
+    atomicAdd(&leb[i], (double)v);
+    return eb[i];
+  }
+  __device__ __forceinline__ R lamj(int c, int x, int y, int z) const {
+    return lj[(DIMS == 3 ? (z - G::j_lo_z) * G::jx : 0) * G::jx + (y - G::j_lo) * G::jx +
+              (x - G::j_lo) + c * G::j_vol];
+  }
+};
+
 // Transpose of the gather: lamF[node] += w lamFp for every stencil node and
 // lamX += sum (dw/dX) F lamFp.
-template <int DIMS, int ORDER, typename R>
-__device__ __forceinline__ void gather_vjp(const KParams<R>& P, const DFields<R>& F,
-                                           R* const* lamE, R* const* lamB, const int* c3,
-                                           const R* o, const R* lEp, const R* lBp, R* lX) {
+template <int DIMS, int ORDER, typename R, class Acc>
+__device__ __forceinline__ void gather_vjp(const Acc& ac, const int* c3, const R* o, const R* lEp,
+                                           const R* lBp, R* lX) {
   constexpr int M = ORDER + 1;
   constexpr int MZ = DIMS == 3 ? M : 1;
   R wn[3][M], ws[3][M], dn[3][M], dsg[3][M];
@@ -88,8 +131,6 @@ __device__ __forceinline__ void gather_vjp(const KParams<R>& P, const DFields<R>
     const bool isb = comp >= 3;
     const int c = isb ? comp - 3 : comp;
     const R lam = isb ? lBp[c] : lEp[c];
-    const R* f = isb ? F.B[c] : F.E[c];
-    R* lf = isb ? lamB[c] : lamE[c];
     const R(*w[3])[M];
     const R(*dw[3])[M];
     int b[3];
@@ -103,12 +144,10 @@ __device__ __forceinline__ void gather_vjp(const KParams<R>& P, const DFields<R>
     for (int k = 0; k < MZ; ++k)
       for (int j = 0; j < M; ++j)
         for (int i = 0; i < M; ++i) {
-          const int g = sample_index<R>(P, DIMS, isb, c, c3[0] + b[0] + i, c3[1] + b[1] + j,
-                                        c3[2] + b[2] + k);
-          if (g < 0) continue;
           const R wx = (*w[0])[i], wy = (*w[1])[j], wz = (*w[2])[k];
-          atomicAdd(&lf[g], wx * wy * wz * lam);
-          const R fl = f[g] * lam;
+          const R fl = ac.field_add(isb, c, c3[0] + b[0] + i, c3[1] + b[1] + j, c3[2] + b[2] + k,
+                                    wx * wy * wz * lam) *
+                       lam;
           lX[0] += (*dw[0])[i] * wy * wz * fl;
           lX[1] += wx * (*dw[1])[j] * wz * fl;
           if (DIMS == 3) lX[2] += wx * wy * (*dw[2])[k] * fl;
@@ -183,8 +222,8 @@ __device__ __forceinline__ void boris_vjp(R hqm, const R* u, const R* E, const R
 
 // Transpose of the Esirkepov deposit of one segment: gathers lamJ over the
 // segment's stencil and returns lam(xa), lam(xb) per axis and lam(fz).
-template <int DIMS, int ORDER, typename R>
-__device__ __forceinline__ void deposit_segment_vjp(const KParams<R>& P, R* const* lamJ,
+template <int DIMS, int ORDER, typename R, class Acc>
+__device__ __forceinline__ void deposit_segment_vjp(const KParams<R>& P, const Acc& ac,
                                                     const int* c3, const int* base, const R* xa,
                                                     const R* xb, R q, R fz, R* lxa, R* lxb,
                                                     R& lfz) {
@@ -211,9 +250,7 @@ __device__ __forceinline__ void deposit_segment_vjp(const KParams<R>& P, R* cons
   }
   lfz = R(0);
   auto lam_at = [&](int comp, int i, int j, int k) -> R {
-    const int g = sample_index<R>(P, DIMS, false, comp, c3[0] + base[0] + i,
-                                  c3[1] + base[1] + j, c3[2] + base[2] + k);
-    return g < 0 ? R(0) : lamJ[comp][g];
+    return ac.lamj(comp, c3[0] + base[0] + i, c3[1] + base[1] + j, c3[2] + base[2] + k);
   };
   (void)MZ;
   if (DIMS == 3) {
@@ -323,8 +360,8 @@ __device__ __forceinline__ void deposit_segment_vjp(const KParams<R>& P, R* cons
 
 // Transpose of the whole split deposit: lamX0, lamX1 (cell units, relative
 // to the old cell) and lam(vz) for the 2D out-of-plane current.
-template <int DIMS, int ORDER, typename R>
-__device__ __forceinline__ void deposit_vjp(const KParams<R>& P, R* const* lamJ, const int* c3,
+template <int DIMS, int ORDER, typename R, class Acc>
+__device__ __forceinline__ void deposit_vjp(const KParams<R>& P, const Acc& ac, const int* c3,
                                             const R* o0, const int* sh, const R* o1, R q, R vz,
                                             R* lX0, R* lX1, R& lvz) {
   Split<DIMS, R> S;
@@ -337,7 +374,7 @@ __device__ __forceinline__ void deposit_vjp(const KParams<R>& P, R* const* lamJ,
     R xa[3], xb[3], ft, lxa[3], lxb[3], lfz;
     int base[3];
     segment_ends<DIMS, ORDER, R>(S, s, xa, xb, base, ft);
-    deposit_segment_vjp<DIMS, ORDER, R>(P, lamJ, c3, base, xa, xb, q, q * vz * ft, lxa, lxb, lfz);
+    deposit_segment_vjp<DIMS, ORDER, R>(P, ac, c3, base, xa, xb, q, q * vz * ft, lxa, lxb, lfz);
     R ta = R(0), tbb = R(1);
 #pragma unroll
     for (int j = 0; j < DIMS + 2; ++j) {
@@ -379,63 +416,203 @@ __device__ __forceinline__ void deposit_vjp(const KParams<R>& P, R* const* lamJ,
   }
 }
 
+// Forward pass of one particle kept for its adjoint: the gather, the Boris
+// push and the move (state s becomes step n+1's, u0 keeps u^{n-1/2}).
+template <typename R>
+struct FwdPart {
+  R Ep[3], Bp[3], u0[3], o1[3], vz;
+  int sh[3];
+  bool small;
+};
+
+template <int DIMS, int ORDER, typename R, class FAcc>
+__device__ __forceinline__ bool forward_part(const KParams<R>& P, const FAcc& acc, PState<R>& s,
+                                             FwdPart<R>& f, DevFlags* flg) {
+  gather<DIMS, ORDER, R>(acc, s.o, f.Ep, f.Bp);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) f.u0[c] = s.u[c];
+  return push_move<DIMS, R>(P, s, f.Ep, f.Bp, f.sh, f.o1, f.vz, f.small, flg);
+}
+
+// Adjoint of one particle's step from its forward pass; c3 are the cell's
+// coordinates in the accessor's frame.  Reads lam at slot p (adjoints of
+// x^{n+1}, u^{n+1/2}) and overwrites it with those of x^n, u^{n-1/2}.
+template <int DIMS, int ORDER, typename R, class Acc>
+__device__ __forceinline__ void adjoint_part(const KParams<R>& P, const Acc& ac, const int* c3,
+                                             const PState<R>& s0, const PState<R>& s1,
+                                             const FwdPart<R>& f, const DParts<R>& lam, int p) {
+  const R u1[3] = {s1.u[0], s1.u[1], s1.u[2]};
+  const R gam = sqrt(R(1) + u1[0] * u1[0] + u1[1] * u1[1] + u1[2] * u1[2]);
+  // adjoints arriving from step n+1
+  R lX1[3] = {R(0), R(0), R(0)}, lX0[3] = {R(0), R(0), R(0)}, lu1[3];
+#pragma unroll
+  for (int d = 0; d < DIMS; ++d) lX1[d] = lam.off[d][p];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) lu1[c] = lam.u[c][p];
+  // deposit
+  R lvz;
+  deposit_vjp<DIMS, ORDER, R>(P, ac, c3, s0.o, f.sh, f.o1, s0.q, f.vz, lX0, lX1, lvz);
+  // move: X1 = X0 + dt/dx u/gamma, vz = u_z/gamma
+  R ld[3] = {R(0), R(0), R(0)};
+  R dot = R(0);
+#pragma unroll
+  for (int d = 0; d < DIMS; ++d) {
+    lX0[d] += lX1[d];
+    ld[d] = lX1[d] * P.dtdx[d];
+    dot += ld[d] * u1[d];
+  }
+  dot += lvz * u1[2];
+  const R ig = R(1) / gam, ig3 = ig * ig * ig;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) lu1[c] += (ld[c] + (c == 2 ? lvz : R(0))) * ig - u1[c] * ig3 * dot;
+  // Boris
+  R lu0[3], lEp[3], lBp[3];
+  boris_vjp<R>(P.hqm, f.u0, f.Ep, f.Bp, lu1, lu0, lEp, lBp);
+  // gather
+  gather_vjp<DIMS, ORDER, R>(ac, c3, s0.o, lEp, lBp, lX0);
+#pragma unroll
+  for (int d = 0; d < DIMS; ++d) lam.off[d][p] = lX0[d];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) lam.u[c][p] = lu0[c];
+}
+
+// One thread per particle, everything in global memory: all particles, or
+// (list != NULL) the flg->ndefer particles of the list followed by those
+// from *tail on (the particles no tile covers).
 template <int DIMS, int ORDER, typename R>
 __global__ void __launch_bounds__(256) k_push_deposit_adjoint(KParams<R> P, DParts<R> pa,
                                                               DFields<R> F, DFields<R> L,
                                                               DParts<R> lam, DevFlags* flg,
-                                                              int np) {
+                                                              int np, const int* list,
+                                                              const int* tail) {
   const int open0 = P.bc[0] == PIC_BC_OPEN, open1 = P.bc[1] == PIC_BC_OPEN;
   const int open2 = DIMS == 3 && P.bc[2] == PIC_BC_OPEN;
-  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < np; p += gridDim.x * blockDim.x) {
+  const int nl = list ? (int)flg->ndefer : 0;
+  const int t0 = list ? *tail : 0;
+  const int n = nl + (np - t0);
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
+    const int p = t < nl ? list[t] : t0 + (t - nl);
     PState<R> s = load_particle<DIMS, R>(pa, p, P.q_const);
     if (s.cl < 0) continue;
     int c3[3];
     if (!decode<DIMS, R>(P, s, c3, flg)) continue;
-    // forward pass of this particle
     GlobalFields<R> acc{F.E, F.B, c3[0], c3[1], c3[2], P.n[0], P.n[1], P.n[2],
                         open0, open1, open2, DIMS};
-    R Ep[3], Bp[3];
-    gather<DIMS, ORDER, R>(acc, s.o, Ep, Bp);
-    const R u0[3] = {s.u[0], s.u[1], s.u[2]};
-    R o1[3], vz;
-    int sh[3];
-    bool small;
-    if (!push_move<DIMS, R>(P, s, Ep, Bp, sh, o1, vz, small, flg)) continue;
-    const R u1[3] = {s.u[0], s.u[1], s.u[2]};
-    const R gam = sqrt(R(1) + u1[0] * u1[0] + u1[1] * u1[1] + u1[2] * u1[2]);
-    // adjoints arriving from step n+1
-    R lX1[3] = {R(0), R(0), R(0)}, lX0[3] = {R(0), R(0), R(0)}, lu1[3];
-#pragma unroll
-    for (int d = 0; d < DIMS; ++d) lX1[d] = lam.off[d][p];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) lu1[c] = lam.u[c][p];
-    // deposit
-    R lvz;
-    deposit_vjp<DIMS, ORDER, R>(P, L.J, c3, s.o, sh, o1, s.q, vz, lX0, lX1, lvz);
-    // move: X1 = X0 + dt/dx u/gamma, vz = u_z/gamma
-    R ld[3] = {R(0), R(0), R(0)};
-    R dot = R(0);
-#pragma unroll
-    for (int d = 0; d < DIMS; ++d) {
-      lX0[d] += lX1[d];
-      ld[d] = lX1[d] * P.dtdx[d];
-      dot += ld[d] * u1[d];
-    }
-    dot += lvz * u1[2];
-    const R ig = R(1) / gam, ig3 = ig * ig * ig;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) lu1[c] += (ld[c] + (c == 2 ? lvz : R(0))) * ig - u1[c] * ig3 * dot;
-    // Boris
-    R lu0[3], lEp[3], lBp[3];
-    boris_vjp<R>(P.hqm, u0, Ep, Bp, lu1, lu0, lEp, lBp);
-    // gather
-    gather_vjp<DIMS, ORDER, R>(P, F, L.E, L.B, c3, s.o, lEp, lBp, lX0);
-#pragma unroll
-    for (int d = 0; d < DIMS; ++d) lam.off[d][p] = lX0[d];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) lam.u[c][p] = lu0[c];
+    const PState<R> s0 = s;
+    FwdPart<R> f;
+    if (!forward_part<DIMS, ORDER, R>(P, acc, s, f, flg)) continue;
+    AdjGlobal<DIMS, R> ac{P, F, L.E, L.B, L.J};
+    adjoint_part<DIMS, ORDER, R>(P, ac, c3, s0, s, f, lam, p);
   }
 }
+
+// The same out of LDS, one workgroup per tile of sorted particles (2D: the
+// field, lamJ and lamE/lamB regions of a tile fit a CU's LDS several times
+// over).  E^n, B^n and lamJ of the tile plus its halo are staged, lamE/lamB
+// accumulate in double in LDS and are added to the global arrays once.
+// Particles outside the tile's drift allowance, or moving half a cell or
+// more, go to the list for the global-memory kernel.
+template <int DIMS, int ORDER, typename R>
+__global__ void __launch_bounds__((Geo<DIMS, ORDER, R>::NT)) k_pda_tile(
+    KParams<R> P, DParts<R> pa, DFields<R> F, DFields<R> L, DParts<R> lam,
+    const int* __restrict__ starts, int* __restrict__ deferred, DevFlags* flg) {
+  using G = Geo<DIMS, ORDER, R>;
+  __shared__ R s_eb[6 * G::e_vol];
+  __shared__ R s_lj[3 * G::j_vol];
+  __shared__ double s_leb[6 * G::e_vol];
+  const int tile = (blockIdx.x & 7) * P.per_xcd + (blockIdx.x >> 3);
+  if (tile >= P.ntiles) return;
+  const int pbeg = starts[tile], pend = starts[tile + 1];
+  if (pbeg == pend) return;
+  int org[3];
+  tile_origin<DIMS, ORDER, R>(P, tile, org);
+  const int open0 = P.bc[0] == PIC_BC_OPEN, open1 = P.bc[1] == PIC_BC_OPEN;
+  const int open2 = DIMS == 3 && P.bc[2] == PIC_BC_OPEN;
+  const int str1 = P.n[0], str2 = P.n[0] * P.n[1];
+  {
+    constexpr int NR = (G::e_vol + G::NT - 1) / G::NT;
+    R stage[NR][6];
+    stage_load<DIMS, ORDER, R, NR>(P, F, org, stage);
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+      const int r = threadIdx.x + k * G::NT;
+      if (r < G::e_vol) {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) s_eb[c * G::e_vol + r] = stage[k][c];
+      }
+    }
+  }
+  for (int r = threadIdx.x; r < G::j_vol; r += G::NT) {  // lamJ_c, staggered along c
+    const int lx = r % G::jx, ly = (r / G::jx) % G::jx, lz = r / (G::jx * G::jx);
+    int sx[2], sy[2], sz[2] = {0, 0};
+    axis_slots(org[0] + G::j_lo + lx, P.n[0], open0, 1, sx);
+    axis_slots(org[1] + G::j_lo + ly, P.n[1], open1, str1, sy);
+    if (DIMS == 3) axis_slots(org[2] + G::j_lo_z + lz, P.n[2], open2, str2, sz);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int ix = sx[c == 0], iy = sy[c == 1], iz = sz[c == 2];
+      s_lj[c * G::j_vol + r] = (ix >= 0 && iy >= 0 && iz >= 0) ? L.J[c][ix + iy + iz] : R(0);
+    }
+  }
+  for (int i = threadIdx.x; i < 6 * G::e_vol; i += G::NT) s_leb[i] = 0.0;
+  __syncthreads();
+  const AdjLds<DIMS, ORDER, R> ac{s_eb, s_lj, s_leb};
+  for (int p = pbeg + threadIdx.x; p < pend; p += G::NT) {
+    PState<R> s = load_particle<DIMS, R>(pa, p, P.q_const);
+    if (s.cl < 0) continue;
+    int c3[3] = {0, 0, 0};
+    if (!decode<DIMS, R>(P, s, c3, flg)) continue;
+    int l[3] = {0, 0, 0};
+    bool fast = true;
+#pragma unroll
+    for (int d = 0; d < DIMS; ++d) {
+      const int Td = d == 2 ? G::TZ : G::T;
+      const int Ad = d == 2 ? G::AZ : G::A;
+      int v = c3[d] - org[d];
+      if (P.bc[d] == PIC_BC_PERIODIC) {
+        v = v < 0 ? v + P.n[d] : v;
+        if (v >= Td + Ad) v -= P.n[d];
+      }
+      l[d] = v;
+      fast = fast && v >= -Ad && v < Td + Ad;
+    }
+    if (!fast) {
+      deferred[atomicAdd(&flg->ndefer, 1u)] = p;
+      continue;
+    }
+    LdsFields<DIMS, ORDER, R> acc{
+        (lds_ptr<const R>)s_eb, ((l[2] - G::e_lo_z) * G::ex + (l[1] - G::e_lo)) * G::ex + (l[0] - G::e_lo)};
+    const PState<R> s0 = s;
+    FwdPart<R> f;
+    if (!forward_part<DIMS, ORDER, R>(P, acc, s, f, flg)) continue;
+    if (!f.small) {
+      deferred[atomicAdd(&flg->ndefer, 1u)] = p;
+      continue;
+    }
+    adjoint_part<DIMS, ORDER, R>(P, ac, l, s0, s, f, lam, p);
+  }
+  __syncthreads();
+  // lamE, lamB of the region (its halo overlaps the neighbouring tiles')
+  for (int r = threadIdx.x; r < G::e_vol; r += G::NT) {
+    const int lx = r % G::ex, ly = (r / G::ex) % G::ex, lz = r / (G::ex * G::ex);
+    int sx[2], sy[2], sz[2] = {0, 0};
+    axis_slots(org[0] + G::e_lo + lx, P.n[0], open0, 1, sx);
+    axis_slots(org[1] + G::e_lo + ly, P.n[1], open1, str1, sy);
+    if (DIMS == 3) axis_slots(org[2] + G::e_lo_z + lz, P.n[2], open2, str2, sz);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {  // E_c staggered along c, B_c along the two others
+      const int e = c < 3 ? c : c - 3;
+      const bool isb = c >= 3;
+      const int ix = sx[isb ? (e != 0) : (e == 0)];
+      const int iy = sy[isb ? (e != 1) : (e == 1)];
+      const int iz = sz[isb ? (e != 2) : (e == 2)];
+      const double v = s_leb[c * G::e_vol + r];
+      if (v != 0.0 && ix >= 0 && iy >= 0 && iz >= 0) atomicAdd(&(isb ? L.B : L.E)[e][ix + iy + iz], (R)v);
+    }
+  }
+}
+
+__global__ void k_adj_reset(DevFlags* flg) { flg->ndefer = 0u; }
 
 template <int DIMS, int ORDER, typename R>
 static int launch_pda(const pic_ctx* ctx, const pic_particles* p, const pic_fields* f,
@@ -465,9 +642,28 @@ static int launch_pda(const pic_ctx* ctx, const pic_particles* p, const pic_fiel
     L.J[c] = (R*)lf->J[c];
   }
   if (p->np == 0) return 0;
+  DevFlags* flg = (DevFlags*)((char*)ws + Lw.flags);
   const long blocks = (p->np + 255) / 256;
-  k_push_deposit_adjoint<DIMS, ORDER, R><<<dim3((unsigned)(blocks < 8192 ? blocks : 8192)), dim3(256), 0, s>>>(
-      P, pa, F, L, la, (DevFlags*)((char*)ws + Lw.flags), (int)p->np);
+  const unsigned gblocks = (unsigned)(blocks < 8192 ? blocks : 8192);
+  // the LDS tile path needs tile bins for these np particles in this
+  // workspace (any particle order is then handled correctly: a particle
+  // outside the allowance of the tile whose range holds it takes the
+  // global-memory kernel)
+  if constexpr (DIMS == 2) {
+    if (ctx->sorted_np == p->np && ctx->sorted_ws == ws) {
+      using G = Geo<DIMS, ORDER, R>;
+      const int* starts = (const int*)((char*)ws + Lw.starts);
+      int* deferred = (int*)((char*)ws + Lw.tmp_cell);
+      k_adj_reset<<<dim3(1), dim3(1), 0, s>>>(flg);
+      k_pda_tile<DIMS, ORDER, R><<<dim3(8 * P.per_xcd), dim3(G::NT), 0, s>>>(P, pa, F, L, la,
+                                                                            starts, deferred, flg);
+      k_push_deposit_adjoint<DIMS, ORDER, R><<<dim3(gblocks), dim3(256), 0, s>>>(
+          P, pa, F, L, la, flg, (int)p->np, deferred, starts + P.ntiles);
+      return (int)hipGetLastError();
+    }
+  }
+  k_push_deposit_adjoint<DIMS, ORDER, R><<<dim3(gblocks), dim3(256), 0, s>>>(
+      P, pa, F, L, la, flg, (int)p->np, nullptr, nullptr);
   return (int)hipGetLastError();
 }
 

@@ -81,78 +81,6 @@ __device__ __forceinline__ int take_batch(int* ctr) {
   return __builtin_amdgcn_readfirstlane(b);
 }
 
-// threadIdx.x behind an opaque copy: index arithmetic on it inside the
-// persistent tile loop stays there instead of being hoisted out of the loop
-// and held in registers across the particle loop.
-__device__ __forceinline__ int opaque_tid() {
-  int t = (int)threadIdx.x;
-  asm volatile("" : "+v"(t));
-  return t;
-}
-
-// E and B of a tile + halo (zero outside open faces) into registers.  Each
-// thread takes region samples and loads the six components there, with the
-// storage offsets along each axis formed once per sample; all loads are in
-// flight together.
-template <int DIMS, int ORDER, typename R, int NR>
-__device__ inline void stage_load(const KParams<R>& P, const DFields<R>& F, const int org[3],
-                                  R (&stage)[NR][6]) {
-  using G = Geo<DIMS, ORDER, R>;
-  const int open0 = P.bc[0] == PIC_BC_OPEN, open1 = P.bc[1] == PIC_BC_OPEN;
-  const int open2 = DIMS == 3 && P.bc[2] == PIC_BC_OPEN;
-  const int str1 = P.n[0], str2 = P.n[0] * P.n[1];
-  const int tid = opaque_tid();
-  const int bx = org[0] + G::e_lo, by = org[1] + G::e_lo, bz = org[2] + G::e_lo_z;
-  if (axis_inside(bx, G::ex, P.n[0], open0) && axis_inside(by, G::ex, P.n[1], open1) &&
-      (DIMS == 2 || axis_inside(bz, G::ez, P.n[2], open2))) {
-    // no wrap, no boundary: one storage offset per sample for all components
-    const int base = (DIMS == 3 ? bz * str2 : 0) + by * str1 + bx;
-#pragma unroll
-    for (int k = 0; k < NR; ++k) {
-      const int r = tid + k * G::NT;
-#pragma unroll
-      for (int c = 0; c < 6; ++c) stage[k][c] = R(0);
-      if (r < G::e_vol) {
-        const int lx = r % G::ex, ly = (r / G::ex) % G::ex, lz = r / (G::ex * G::ex);
-        const int o = base + (DIMS == 3 ? lz * str2 : 0) + ly * str1 + lx;
-#pragma unroll
-        for (int c = 0; c < 6; ++c) stage[k][c] = (c >= 3 ? F.B[c - 3] : F.E[c])[o];
-      }
-    }
-    return;
-  }
-#pragma unroll
-  for (int k = 0; k < NR; ++k) {
-    const int r = tid + k * G::NT;
-#pragma unroll
-    for (int c = 0; c < 6; ++c) stage[k][c] = R(0);
-    if (r < G::e_vol) {
-      const int lx = r % G::ex, ly = (r / G::ex) % G::ex, lz = r / (G::ex * G::ex);
-      int sx[2], sy[2], sz[2] = {0, 0};
-      axis_slots(org[0] + G::e_lo + lx, P.n[0], open0, 1, sx);
-      axis_slots(org[1] + G::e_lo + ly, P.n[1], open1, str1, sy);
-      if (DIMS == 3) axis_slots(org[2] + G::e_lo_z + lz, P.n[2], open2, str2, sz);
-#pragma unroll
-      for (int c = 0; c < 6; ++c) {  // E_c staggered along c, B_c along the two others
-        const int e = c < 3 ? c : c - 3;
-        const bool isb = c >= 3;
-        const int ix = sx[isb ? (e != 0) : (e == 0)];
-        const int iy = sy[isb ? (e != 1) : (e == 1)];
-        const int iz = sz[isb ? (e != 2) : (e == 2)];
-        if (ix >= 0 && iy >= 0 && iz >= 0) stage[k][c] = (isb ? F.B[e] : F.E[e])[ix + iy + iz];
-      }
-    }
-  }
-}
-
-template <int DIMS, int ORDER, typename R>
-__device__ inline void tile_origin(const KParams<R>& P, int tile, int org[3]) {
-  using G = Geo<DIMS, ORDER, R>;
-  org[0] = (tile % P.ntile[0]) * G::T;
-  org[1] = ((tile / P.ntile[0]) % P.ntile[1]) * G::T;
-  org[2] = (tile / (P.ntile[0] * P.ntile[1])) * G::TZ;
-}
-
 // Tile kernel: persistent workgroups, each taking tiles until none is left;
 // particles within the drift allowance of the tile run out of LDS.  Any
 // other particle (drifted further, or moving half a cell or more in one

@@ -207,3 +207,51 @@ def test_rollout_gradient_matches_central_differences_fp64():
     say("fd", fd_a0, float(a0.grad), fd_v, g_v)
     assert abs(float(a0.grad) - fd_a0) <= 1e-6 * abs(fd_a0)
     assert abs(g_v - fd_v) <= 1e-6 * max(abs(fd_v), 1e-3 * abs(fd_a0))
+
+
+@pytest.mark.parametrize("rb,order", [(8, 2), (4, 2), (8, 3)])
+def test_tiled_step_adjoint_equals_global_memory_adjoint(rb, order):
+    """In 2D the step adjoint runs out of LDS when the context holds tile bins
+    for the particles (same count, same workspace), else one thread per
+    particle in global memory.  Both must give the same lamX, lamU, lamE,
+    lamB, also for particles in an order other than the sort's (they take
+    the global-memory path inside the tiled call)."""
+    from paper_1310_0930_amd import pic as P
+    lz = I.Laser(a0=2.0, omega0=4.0, waist=1.0, tau=0.4, x_center=1.2)
+    w = I.Workload("adjt", 2, (48, 32), (0.1, 0.2), order, 6, 0.2, 1, bc=(0, 1),
+                   ramp_cells=6.0, laser=lz, seed=I.SEED_BASE + 120 + order)
+    pl, E, B = inputs_for(w)
+    sim = _sim(w, rb)
+    sim.load(pl, E, B, with_id=True)
+    sim.sort()
+    rng = np.random.default_rng(31 + order)
+    shp = (3, sim.ncell)
+    lE0, lB0, lJ0 = (_t(rng.normal(size=shp), sim) for _ in range(3))
+    lX0 = _t(rng.normal(size=(3, sim.np)), sim)
+    lU0 = _t(rng.normal(size=(3, sim.np)), sim)
+    other_ws = torch.zeros_like(sim.ws)
+
+    def run(perm, ws):
+        cell, off, u = sim.cell[perm].clone(), sim.off[:, perm].clone(), sim.u[:, perm].clone()
+        q = None if sim.q is None else sim.q[perm].clone()
+        LE, LB, LJ = lE0.clone(), lB0.clone(), lJ0.clone()
+        LX, LU = lX0[:, perm].clone(), lU0[:, perm].clone()
+        P.pic_push_deposit_adjoint(sim.ctx, P.particles_struct(sim.np, cell, off, u, q),
+                                   P.fields_struct(sim.E, sim.B), P.fields_struct(LE, LB, LJ),
+                                   P.particles_struct(sim.np, None, LX, LU), ws.data_ptr(), sim.stream)
+        torch.cuda.synchronize()
+        inv = torch.empty_like(perm)
+        inv[perm] = torch.arange(perm.numel(), device=perm.device)
+        return [t.double().cpu().numpy() for t in (LE, LB, LX[:, inv], LU[:, inv])]
+
+    ident = torch.arange(sim.np, device=sim.device)
+    shuffled = torch.from_numpy(rng.permutation(sim.np)).to(sim.device)
+    tiled = run(ident, sim.ws)            # LDS tiles (sorted order)
+    glob = run(ident, other_ws)           # no tile bins in this workspace
+    mixed = run(shuffled, sim.ws)         # tile bins, particles in another order
+    tol = 1e-11 if rb == 8 else 2e-4
+    for name, a, b, c in zip(("lamE", "lamB", "lamX", "lamU"), tiled, glob, mixed):
+        scale = np.abs(b).max() + 1e-30
+        say("tiled vs global", order, rb, name, np.abs(a - b).max() / scale, np.abs(c - b).max() / scale)
+        assert np.abs(a - b).max() <= tol * scale, name
+        assert np.abs(c - b).max() <= tol * scale, name
