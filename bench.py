@@ -41,6 +41,26 @@ def algorithmic_bytes(w, np_, real_bytes):
     return np_ * per_particle + w.ncell * per_cell * nspecies
 
 
+# Conflict-free LDS atomic rates of this chip (G lane-ops/s, whole GPU), from
+# a microbenchmark of ds_add_u64 and ds_add_f64 over 16 waves per CU.
+LDS_ATOMIC_PEAK = {4: 3714.0, 8: 3423.0}
+
+
+def lds_atomics(w, np_, push_ms, real_bytes):
+    """LDS atomic throughput of the push/deposit tile kernel against the
+    conflict-free rate: the Esirkepov current of each particle's first virtual
+    segment adds 3 n (n+1)^2 samples in 3D and 2 n (n+1) + (n+1)^2 in 2D3V (a
+    lower bound: the few particles that cross a stencil plane add more)."""
+    n = w.order
+    per = 3 * n * (n + 1) ** 2 if w.dims == 3 else 2 * n * (n + 1) + (n + 1) ** 2
+    ops = per * np_
+    ach = ops / (push_ms * 1e-3) / 1e9
+    peak = LDS_ATOMIC_PEAK[real_bytes]
+    return {"op": "ds_add_u64 (exact fixed point)" if real_bytes == 4 else "ds_add_f64",
+            "lane_ops_per_launch": int(ops), "achieved": round(ach, 1), "peak": peak,
+            "unit": "G lane-ops/s", "frac": round(ach / peak, 4)}
+
+
 def kernel_hash():
     h = hashlib.sha256()
     for f in ("k_push.hip", "k_particle.h", "k_common.h", "pic_internal.h"):
@@ -265,13 +285,16 @@ def main():
                    "parallelism": "single GPU"},
         "push_deposit_pushes_per_s": r32["np"] / (r32["push_ms_mean"] * 1e-3),
         "roofline": roof(r32, 4, "f32"),
+        "lds_atomics": lds_atomics(w, r32["np"], r32["push_ms_mean"], 4),
         "slowpath_pushes": r32["slowpath"], "device_flags": r32["flags"],
     }
     if r64:
         out["fp64"] = {"value": r64["np"] / (r64["ms_per_step"] * 1e-3),
                        "ms_per_step": round(r64["ms_per_step"], 5),
                        "push_deposit_pushes_per_s": r64["np"] / (r64["push_ms_mean"] * 1e-3),
-                       "roofline": roof(r64, 8, "f64"), "device_flags": r64["flags"]}
+                       "roofline": roof(r64, 8, "f64"),
+                       "lds_atomics": lds_atomics(w, r64["np"], r64["push_ms_mean"], 8),
+                       "device_flags": r64["flags"]}
     if a.window > 0:
         out["window_shift"] = {"f32": run_window(w, 4, a.window, log)}
         if not a.no_fp64:
