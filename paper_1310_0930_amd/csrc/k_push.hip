@@ -1,5 +1,6 @@
 // Fused gather + relativistic Boris push + move + trajectory split +
-// charge-conserving (Esirkepov) deposit, one workgroup per tile.
+// charge-conserving (Esirkepov) deposit, tile by tile (persistent
+// workgroups, one tile at a time each).
 //
 // This is the per-particle body of the PIC loop (Sec. 2) in the order of the
 // paper's vector algorithm (Sec. 5.2, steps i-v).  The paper vectorises it
@@ -9,7 +10,8 @@
 // 64-wide wavefront lane owns a particle; the workgroup stages the E and B
 // samples of its tile (plus halo) in LDS once, so the gather is a set of
 // LDS reads at compile-time offsets, and accumulates the current of every
-// virtual segment into an LDS tile with LDS float atomics before one
+// virtual segment into an LDS tile with LDS atomics (exact 64-bit fixed
+// point in the single-precision form, double in the double form) before one
 // coalesced flush with global atomics where tile halos overlap.
 //
 // Positions are an integer cell plus an offset in [0,1) normalised to the
