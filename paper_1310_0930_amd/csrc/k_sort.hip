@@ -252,33 +252,10 @@ __global__ void k_sort_scatter(SortArrays<R> A, long np, int ncell, int dims,
   if (A.q) A.t_q[dst] = qv;
 }
 
-// Copy of particle i of the scatter's arrays to slot j of the particle
-// arrays: every load first, then every store (a store to one array may
-// alias a later load of another as far as the compiler knows, which would
-// serialize the round trips).
-template <typename R>
-__device__ __forceinline__ void copy_back(const SortArrays<R>& A, long i, long j, int dims) {
-  const int cl = A.t_cell[i];
-  R o[3] = {R(0), R(0), R(0)}, u[3];
-#pragma unroll
-  for (int d = 0; d < 3; ++d)
-    if (d < dims) o[d] = A.t_off[d][i];
-#pragma unroll
-  for (int c = 0; c < 3; ++c) u[c] = A.t_u[c][i];
-  const R qv = A.q ? A.t_q[i] : R(0);
-  const int idv = A.id ? A.t_id[i] : 0;
-  const_cast<int*>(A.cell)[j] = cl;
-#pragma unroll
-  for (int d = 0; d < 3; ++d)
-    if (d < dims) const_cast<R*>(A.off[d])[j] = o[d];
-#pragma unroll
-  for (int c = 0; c < 3; ++c) const_cast<R*>(A.u[c])[j] = u[c];
-  if (A.q) const_cast<R*>(A.q)[j] = qv;
-  if (A.id) const_cast<int*>(A.id)[j] = idv;
-}
-
-// One particle's payload in registers (for batched copies: all loads of a
-// batch are in flight together).
+// One particle's payload in registers: every load first, then every store
+// (a store to one array may alias a later load of another as far as the
+// compiler knows, which would serialize the round trips), and batched
+// copies keep all loads of a batch in flight together.
 template <typename R>
 struct PVal {
   int cl, id;
@@ -309,8 +286,11 @@ template <typename R>
 __global__ void k_sort_copyback_dead(SortArrays<R> A, const int* __restrict__ dead_start, long np,
                                      int dims) {
   for (long i = *dead_start + blockIdx.x * (long)blockDim.x + threadIdx.x; i < np;
-       i += (long)gridDim.x * blockDim.x)
-    copy_back(A, i, i, dims);
+       i += (long)gridDim.x * blockDim.x) {
+    PVal<R> v;
+    v.load(A, i, dims);
+    v.store(A, i, dims);
+  }
 }
 
 // In-bin order of a tile's cells.  A bin's cells hold one particle each
