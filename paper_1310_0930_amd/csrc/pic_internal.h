@@ -62,8 +62,10 @@ struct Geo {
   // threads per workgroup: in 3D one workgroup fills a CU's LDS, so it
   // brings all the wavefronts: 16 (4 per SIMD, <= 128 VGPRs) in FP32 up to
   // cubic order, 8 for FP64 and quartic, whose gather and deposit need more
-  // registers; 2D tiles are small and several workgroups share a CU
-  static constexpr int NT = DIMS == 2 ? 256 : (sizeof(R) == 4 && ORDER <= 3 ? 1024 : 512);
+  // registers; 2D tiles are small and several workgroups share a CU, with
+  // 8 wavefronts each so that a workgroup's batches drain its tile sooner
+  // (a 512 x 256 mesh has only 512 tiles of 16 x 16 for 256 CUs)
+  static constexpr int NT = DIMS == 2 ? 512 : (sizeof(R) == 4 && ORDER <= 3 ? 1024 : 512);
 };
 
 // Unsigned division by a runtime divisor through a precomputed multiplier
