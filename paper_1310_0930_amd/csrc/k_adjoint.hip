@@ -83,9 +83,41 @@ struct AdjGlobal {
   }
 };
 
+// Region of one workgroup of the LDS adjoint: the push tile, cut along z
+// into S slabs when the three regions (E/B and lamJ in the working
+// precision, lamE/lamB in double) of a whole 3D tile exceed a CU's LDS.
+// Each slab keeps the tile's drift allowance and stencil reach; x and y are
+// the tile's.  `fits` is false where even one-cell slabs do not fit (cubic
+// in double precision), and that form keeps the global-memory kernel.
 template <int DIMS, int ORDER, typename R>
+struct AdjGeo : Geo<DIMS, ORDER, R> {
+  using B = Geo<DIMS, ORDER, R>;
+  using Rc = typename B::Rc;
+  static constexpr size_t bytes(int tz) {
+    return (sizeof(R) * 6 + sizeof(double) * 6) * (size_t)(B::ex * B::ex * (tz + 2 * B::AZ + Rc::g_hi - Rc::g_lo)) +
+           sizeof(R) * 3 * (size_t)(B::jx * B::jx * (tz + 2 * B::AZ + Rc::d_hi - Rc::d_lo));
+  }
+  static constexpr size_t LDS_MAX = 160 * 1024;
+  static constexpr int pick() {
+    if (DIMS == 2) return 1;
+    for (int s = 1; s <= B::TZ; s *= 2)
+      if (B::TZ % s == 0 && bytes(B::TZ / s) <= LDS_MAX) return s;
+    return 0;
+  }
+  static constexpr int S = pick();
+  static constexpr bool fits = S > 0;
+  static constexpr int TZ = fits ? B::TZ / S : 1;
+  static constexpr int ez = DIMS == 3 ? TZ + 2 * B::AZ + Rc::g_hi - Rc::g_lo : 1;
+  static constexpr int e_vol = B::ex * B::ex * ez;
+  static constexpr int jz = DIMS == 3 ? TZ + 2 * B::AZ + Rc::d_hi - Rc::d_lo : 1;
+  static constexpr int j_vol = B::jx * B::jx * jz;
+  // 2D: several workgroups share a CU; 3D: one per CU, 8 wavefronts of up
+  // to 256 VGPRs
+  static constexpr int NT = DIMS == 2 ? 256 : 512;
+};
+
+template <int DIMS, int ORDER, typename R, class G>
 struct AdjLds {
-  using G = Geo<DIMS, ORDER, R>;
   const R* eb;   // E^n (0..2), B^n (3..5) over the field region
   const R* lj;   // lamJ over the current region
   double* leb;   // lamE (0..2), lamB (3..5) over the field region
@@ -506,33 +538,40 @@ __global__ void __launch_bounds__(256) k_push_deposit_adjoint(KParams<R> P, DPar
   }
 }
 
-// The same out of LDS, one workgroup per tile of sorted particles (2D: the
-// field, lamJ and lamE/lamB regions of a tile fit a CU's LDS several times
-// over).  E^n, B^n and lamJ of the tile plus its halo are staged, lamE/lamB
-// accumulate in double in LDS and are added to the global arrays once.
-// Particles outside the tile's drift allowance, or moving half a cell or
-// more, go to the list for the global-memory kernel.
+// The same out of LDS, one workgroup per tile of sorted particles, or per z
+// slab of one in 3D (AdjGeo): E^n, B^n and lamJ of the region are staged,
+// lamE/lamB accumulate in double in LDS and are added to the global arrays
+// once.  Every slab reads all of its tile's particles and takes those whose
+// cell is in the slab, the first and last slabs also the allowance below
+// and above the tile.  Particles outside the tile's drift allowance, or
+// moving half a cell or more, go to the list for the global-memory kernel
+// (entered by the first slab alone).
 template <int DIMS, int ORDER, typename R>
-__global__ void __launch_bounds__((Geo<DIMS, ORDER, R>::NT)) k_pda_tile(
+__global__ void __launch_bounds__((AdjGeo<DIMS, ORDER, R>::NT)) k_pda_tile(
     KParams<R> P, DParts<R> pa, DFields<R> F, DFields<R> L, DParts<R> lam,
     const int* __restrict__ starts, int* __restrict__ deferred, DevFlags* flg) {
-  using G = Geo<DIMS, ORDER, R>;
+  using G = AdjGeo<DIMS, ORDER, R>;
+  constexpr int S = G::S;
   __shared__ R s_eb[6 * G::e_vol];
   __shared__ R s_lj[3 * G::j_vol];
   __shared__ double s_leb[6 * G::e_vol];
-  const int tile = (blockIdx.x & 7) * P.per_xcd + (blockIdx.x >> 3);
+  const int grp = blockIdx.x >> 3;
+  const int tile = (blockIdx.x & 7) * P.per_xcd + grp / S;
+  const int slab = grp % S;
   if (tile >= P.ntiles) return;
   const int pbeg = starts[tile], pend = starts[tile + 1];
   if (pbeg == pend) return;
   int org[3];
   tile_origin<DIMS, ORDER, R>(P, tile, org);
+  const int torg2 = org[2];
+  org[2] += slab * G::TZ;
   const int open0 = P.bc[0] == PIC_BC_OPEN, open1 = P.bc[1] == PIC_BC_OPEN;
   const int open2 = DIMS == 3 && P.bc[2] == PIC_BC_OPEN;
   const int str1 = P.n[0], str2 = P.n[0] * P.n[1];
   {
     constexpr int NR = (G::e_vol + G::NT - 1) / G::NT;
     R stage[NR][6];
-    stage_load<DIMS, ORDER, R, NR>(P, F, org, stage);
+    stage_load<DIMS, ORDER, R, NR, G>(P, F, org, stage);
 #pragma unroll
     for (int k = 0; k < NR; ++k) {
       const int r = threadIdx.x + k * G::NT;
@@ -556,19 +595,20 @@ __global__ void __launch_bounds__((Geo<DIMS, ORDER, R>::NT)) k_pda_tile(
   }
   for (int i = threadIdx.x; i < 6 * G::e_vol; i += G::NT) s_leb[i] = 0.0;
   __syncthreads();
-  const AdjLds<DIMS, ORDER, R> ac{s_eb, s_lj, s_leb};
+  const AdjLds<DIMS, ORDER, R, G> ac{s_eb, s_lj, s_leb};
   for (int p = pbeg + threadIdx.x; p < pend; p += G::NT) {
     PState<R> s = load_particle<DIMS, R>(pa, p, P.q_const);
     if (s.cl < 0) continue;
     int c3[3] = {0, 0, 0};
     if (!decode<DIMS, R>(P, s, c3, flg)) continue;
+    const int tor[3] = {org[0], org[1], torg2};
     int l[3] = {0, 0, 0};
     bool fast = true;
 #pragma unroll
     for (int d = 0; d < DIMS; ++d) {
-      const int Td = d == 2 ? G::TZ : G::T;
+      const int Td = d == 2 ? G::B::TZ : G::T;
       const int Ad = d == 2 ? G::AZ : G::A;
-      int v = c3[d] - org[d];
+      int v = c3[d] - tor[d];
       if (P.bc[d] == PIC_BC_PERIODIC) {
         v = v < 0 ? v + P.n[d] : v;
         if (v >= Td + Ad) v -= P.n[d];
@@ -577,10 +617,15 @@ __global__ void __launch_bounds__((Geo<DIMS, ORDER, R>::NT)) k_pda_tile(
       fast = fast && v >= -Ad && v < Td + Ad;
     }
     if (!fast) {
-      deferred[atomicAdd(&flg->ndefer, 1u)] = p;
+      if (slab == 0) deferred[atomicAdd(&flg->ndefer, 1u)] = p;
       continue;
     }
-    LdsFields<DIMS, ORDER, R> acc{
+    if (S > 1) {  // the slab of the particle's cell (allowance cells go to the end slabs)
+      const int k = l[2] < 0 ? 0 : (l[2] / G::TZ < S ? l[2] / G::TZ : S - 1);
+      if (k != slab) continue;
+      l[2] -= slab * G::TZ;
+    }
+    LdsFields<DIMS, ORDER, R, G> acc{
         (lds_ptr<const R>)s_eb, ((l[2] - G::e_lo_z) * G::ex + (l[1] - G::e_lo)) * G::ex + (l[0] - G::e_lo)};
     const PState<R> s0 = s;
     FwdPart<R> f;
@@ -592,7 +637,7 @@ __global__ void __launch_bounds__((Geo<DIMS, ORDER, R>::NT)) k_pda_tile(
     adjoint_part<DIMS, ORDER, R>(P, ac, l, s0, s, f, lam, p);
   }
   __syncthreads();
-  // lamE, lamB of the region (its halo overlaps the neighbouring tiles')
+  // lamE, lamB of the region (its halo overlaps the neighbouring regions')
   for (int r = threadIdx.x; r < G::e_vol; r += G::NT) {
     const int lx = r % G::ex, ly = (r / G::ex) % G::ex, lz = r / (G::ex * G::ex);
     int sx[2], sy[2], sz[2] = {0, 0};
@@ -649,13 +694,13 @@ static int launch_pda(const pic_ctx* ctx, const pic_particles* p, const pic_fiel
   // workspace (any particle order is then handled correctly: a particle
   // outside the allowance of the tile whose range holds it takes the
   // global-memory kernel)
-  if constexpr (DIMS == 2) {
+  if constexpr (AdjGeo<DIMS, ORDER, R>::fits) {
     if (ctx->sorted_np == p->np && ctx->sorted_ws == ws) {
-      using G = Geo<DIMS, ORDER, R>;
+      using G = AdjGeo<DIMS, ORDER, R>;
       const int* starts = (const int*)((char*)ws + Lw.starts);
       int* deferred = (int*)((char*)ws + Lw.tmp_cell);
       k_adj_reset<<<dim3(1), dim3(1), 0, s>>>(flg);
-      k_pda_tile<DIMS, ORDER, R><<<dim3(8 * P.per_xcd), dim3(G::NT), 0, s>>>(P, pa, F, L, la,
+      k_pda_tile<DIMS, ORDER, R><<<dim3(8 * P.per_xcd * G::S), dim3(G::NT), 0, s>>>(P, pa, F, L, la,
                                                                             starts, deferred, flg);
       k_push_deposit_adjoint<DIMS, ORDER, R><<<dim3(gblocks), dim3(256), 0, s>>>(
           P, pa, F, L, la, flg, (int)p->np, deferred, starts + P.ntiles);

@@ -110,9 +110,8 @@ __device__ __forceinline__ void dshape(R xa, R xb, R* d) {
 template <typename T>
 using lds_ptr = __attribute__((address_space(3))) T*;
 
-template <int DIMS, int ORDER, typename R>
+template <int DIMS, int ORDER, typename R, class G = Geo<DIMS, ORDER, R>>
 struct LdsFields {
-  using G = Geo<DIMS, ORDER, R>;
   lds_ptr<const R> s;
   int base;
   __device__ __forceinline__ lds_ptr<const R> ref(int comp, const int* b) const {
@@ -661,14 +660,14 @@ __device__ __forceinline__ int opaque_tid() {
   return t;
 }
 
-// E and B of a tile + halo (zero outside open faces) into registers.  Each
+// E and B of a tile + halo (zero outside open faces) into registers (G: the
+// region's geometry, the push tile's by default).  Each
 // thread takes region samples and loads the six components there, with the
 // storage offsets along each axis formed once per sample; all loads are in
 // flight together.
-template <int DIMS, int ORDER, typename R, int NR>
+template <int DIMS, int ORDER, typename R, int NR, class G = Geo<DIMS, ORDER, R>>
 __device__ inline void stage_load(const KParams<R>& P, const DFields<R>& F, const int org[3],
                                   R (&stage)[NR][6]) {
-  using G = Geo<DIMS, ORDER, R>;
   const int open0 = P.bc[0] == PIC_BC_OPEN, open1 = P.bc[1] == PIC_BC_OPEN;
   const int open2 = DIMS == 3 && P.bc[2] == PIC_BC_OPEN;
   const int str1 = P.n[0], str2 = P.n[0] * P.n[1];

@@ -209,17 +209,26 @@ def test_rollout_gradient_matches_central_differences_fp64():
     assert abs(g_v - fd_v) <= 1e-6 * max(abs(fd_v), 1e-3 * abs(fd_a0))
 
 
-@pytest.mark.parametrize("rb,order", [(8, 2), (4, 2), (8, 3)])
-def test_tiled_step_adjoint_equals_global_memory_adjoint(rb, order):
-    """In 2D the step adjoint runs out of LDS when the context holds tile bins
-    for the particles (same count, same workspace), else one thread per
-    particle in global memory.  Both must give the same lamX, lamU, lamE,
-    lamB, also for particles in an order other than the sort's (they take
-    the global-memory path inside the tiled call)."""
+@pytest.mark.parametrize("dims,rb,order", [(2, 8, 2), (2, 4, 2), (2, 8, 3), (3, 8, 1), (3, 4, 1),
+                                           (3, 8, 2), (3, 4, 2), (3, 4, 3), (3, 8, 4), (3, 4, 4)])
+def test_tiled_step_adjoint_equals_global_memory_adjoint(dims, rb, order):
+    """The step adjoint runs out of LDS when the context holds tile bins for
+    the particles (same count, same workspace), else one thread per particle
+    in global memory.  In 3D a tile is cut into z slabs (one per workgroup)
+    where its regions exceed a CU's LDS: 2 slabs for quadratic FP32, 4 for
+    cubic FP32 and quartic FP64, one-cell slabs for quartic FP32; the 3D
+    grid here has a ragged last tile along z and an open face.  Both paths
+    must give the same lamX, lamU, lamE, lamB, also for particles in an
+    order other than the sort's (they take the global-memory path inside
+    the tiled call)."""
     from paper_1310_0930_amd import pic as P
-    lz = I.Laser(a0=2.0, omega0=4.0, waist=1.0, tau=0.4, x_center=1.2)
-    w = I.Workload("adjt", 2, (48, 32), (0.1, 0.2), order, 6, 0.2, 1, bc=(0, 1),
-                   ramp_cells=6.0, laser=lz, seed=I.SEED_BASE + 120 + order)
+    if dims == 2:
+        lz = I.Laser(a0=2.0, omega0=4.0, waist=1.0, tau=0.4, x_center=1.2)
+        w = I.Workload("adjt", 2, (48, 32), (0.1, 0.2), order, 6, 0.2, 1, bc=(0, 1),
+                       ramp_cells=6.0, laser=lz, seed=I.SEED_BASE + 120 + order)
+    else:
+        w = I.Workload("adjt3", 3, (24, 16, 20), (0.2, 0.25, 0.2), order, 4, 0.3, 1,
+                       bc=(0, 1, 0), ramp_cells=4.0, seed=I.SEED_BASE + 130 + order)
     pl, E, B = inputs_for(w)
     sim = _sim(w, rb)
     sim.load(pl, E, B, with_id=True)
@@ -252,6 +261,6 @@ def test_tiled_step_adjoint_equals_global_memory_adjoint(rb, order):
     tol = 1e-11 if rb == 8 else 2e-4
     for name, a, b, c in zip(("lamE", "lamB", "lamX", "lamU"), tiled, glob, mixed):
         scale = np.abs(b).max() + 1e-30
-        say("tiled vs global", order, rb, name, np.abs(a - b).max() / scale, np.abs(c - b).max() / scale)
+        say("tiled vs global", dims, order, rb, name, np.abs(a - b).max() / scale, np.abs(c - b).max() / scale)
         assert np.abs(a - b).max() <= tol * scale, name
         assert np.abs(c - b).max() <= tol * scale, name
