@@ -261,10 +261,12 @@ int pic_field_advance_adjoint(pic_ctx* ctx, pic_fields* lam, void* ws, void* str
  * contribution is ADDED (atomics).  lam_p->off[d] (cell units) and
  * lam_p->u[c]: in, adjoints of x^{n+1} and u^{n+1/2}; out, adjoints of x^n and
  * u^{n-1/2}, slot by slot with state_n (lam_p->cell, q, id are unused).
- * Absorbed particles (cell = -1) are skipped.  In 2D, when the context's last
+ * Absorbed particles (cell = -1) are skipped.  When the context's last
  * pic_sort was of state_n->np particles in this `ws`, particles inside the
  * drift allowance of the tile whose bin range holds them are done out of
- * LDS (the rest in global memory); the result does not depend on that. */
+ * LDS, per tile in 2D and per z slab of a tile in 3D (the rest, and every
+ * particle of the cubic FP64 form, in global memory); the result does not
+ * depend on that beyond the order of floating-point atomic additions. */
 int pic_push_deposit_adjoint(pic_ctx* ctx, const pic_particles* state_n, const pic_fields* EB_n,
                              pic_fields* lam_f, pic_particles* lam_p, void* ws, void* stream);
 
