@@ -15,8 +15,8 @@
  * interpolation, equations of motion, virtual-particle trajectory splitting,
  * charge-conserving current deposition).  The paper prints no equations; the
  * concrete readings (normalised units, Boris pusher, Yee layout, B-spline
- * shapes, split-then-Esirkepov deposition, Mur-1 open faces) are listed in
- * the design doc of this repository and restated beside each function below.
+ * shapes, split-then-Esirkepov deposition, Mur-1 open faces) are stated
+ * beside each function below.
  *
  * Layout: positions are global, in cell units (X_d = x_d / dx_d), FP64, three
  * per particle (the z entry is ignored in 2D).  Field arrays are
