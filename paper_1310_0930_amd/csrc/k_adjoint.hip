@@ -98,10 +98,17 @@ struct AdjGeo : Geo<DIMS, ORDER, R> {
            sizeof(R) * 3 * (size_t)(B::jx * B::jx * (tz + 2 * B::AZ + Rc::d_hi - Rc::d_lo));
   }
   static constexpr size_t LDS_MAX = 160 * 1024;
+  // 2D: several workgroups share a CU; 3D: one per CU, 8 wavefronts of up
+  // to 256 VGPRs
+  static constexpr int NT = DIMS == 2 ? 256 : 512;
+  // with several slabs each wavefront queues the particles of its slab:
+  // 128 indices per wavefront
+  static constexpr int QCAP = 128;
+  static constexpr size_t queue_bytes = sizeof(int) * QCAP * (NT / 64);
   static constexpr int pick() {
     if (DIMS == 2) return 1;
     for (int s = 1; s <= B::TZ; s *= 2)
-      if (B::TZ % s == 0 && bytes(B::TZ / s) <= LDS_MAX) return s;
+      if (B::TZ % s == 0 && bytes(B::TZ / s) + (s > 1 ? queue_bytes : 0) <= LDS_MAX) return s;
     return 0;
   }
   static constexpr int S = pick();
@@ -111,9 +118,6 @@ struct AdjGeo : Geo<DIMS, ORDER, R> {
   static constexpr int e_vol = B::ex * B::ex * ez;
   static constexpr int jz = DIMS == 3 ? TZ + 2 * B::AZ + Rc::d_hi - Rc::d_lo : 1;
   static constexpr int j_vol = B::jx * B::jx * jz;
-  // 2D: several workgroups share a CU; 3D: one per CU, 8 wavefronts of up
-  // to 256 VGPRs
-  static constexpr int NT = DIMS == 2 ? 256 : 512;
 };
 
 template <int DIMS, int ORDER, typename R, class G>
@@ -596,45 +600,120 @@ __global__ void __launch_bounds__((AdjGeo<DIMS, ORDER, R>::NT)) k_pda_tile(
   for (int i = threadIdx.x; i < 6 * G::e_vol; i += G::NT) s_leb[i] = 0.0;
   __syncthreads();
   const AdjLds<DIMS, ORDER, R, G> ac{s_eb, s_lj, s_leb};
-  for (int p = pbeg + threadIdx.x; p < pend; p += G::NT) {
-    PState<R> s = load_particle<DIMS, R>(pa, p, P.q_const);
-    if (s.cl < 0) continue;
-    int c3[3] = {0, 0, 0};
-    if (!decode<DIMS, R>(P, s, c3, flg)) continue;
-    const int tor[3] = {org[0], org[1], torg2};
-    int l[3] = {0, 0, 0};
-    bool fast = true;
+  if constexpr (S == 1) {
+    for (int p = pbeg + threadIdx.x; p < pend; p += G::NT) {
+      PState<R> s = load_particle<DIMS, R>(pa, p, P.q_const);
+      if (s.cl < 0) continue;
+      int c3[3] = {0, 0, 0};
+      if (!decode<DIMS, R>(P, s, c3, flg)) continue;
+      const int tor[3] = {org[0], org[1], torg2};
+      int l[3] = {0, 0, 0};
+      bool fast = true;
 #pragma unroll
-    for (int d = 0; d < DIMS; ++d) {
-      const int Td = d == 2 ? G::B::TZ : G::T;
-      const int Ad = d == 2 ? G::AZ : G::A;
-      int v = c3[d] - tor[d];
-      if (P.bc[d] == PIC_BC_PERIODIC) {
-        v = v < 0 ? v + P.n[d] : v;
-        if (v >= Td + Ad) v -= P.n[d];
+      for (int d = 0; d < DIMS; ++d) {
+        const int Td = d == 2 ? G::B::TZ : G::T;
+        const int Ad = d == 2 ? G::AZ : G::A;
+        int v = c3[d] - tor[d];
+        if (P.bc[d] == PIC_BC_PERIODIC) {
+          v = v < 0 ? v + P.n[d] : v;
+          if (v >= Td + Ad) v -= P.n[d];
+        }
+        l[d] = v;
+        fast = fast && v >= -Ad && v < Td + Ad;
       }
-      l[d] = v;
-      fast = fast && v >= -Ad && v < Td + Ad;
+      if (!fast) {
+        if (slab == 0) deferred[atomicAdd(&flg->ndefer, 1u)] = p;
+        continue;
+      }
+      LdsFields<DIMS, ORDER, R, G> acc{
+          (lds_ptr<const R>)s_eb, ((l[2] - G::e_lo_z) * G::ex + (l[1] - G::e_lo)) * G::ex + (l[0] - G::e_lo)};
+      const PState<R> s0 = s;
+      FwdPart<R> f;
+      if (!forward_part<DIMS, ORDER, R>(P, acc, s, f, flg)) continue;
+      if (!f.small) {
+        deferred[atomicAdd(&flg->ndefer, 1u)] = p;
+        continue;
+      }
+      adjoint_part<DIMS, ORDER, R>(P, ac, l, s0, s, f, lam, p);
     }
-    if (!fast) {
-      if (slab == 0) deferred[atomicAdd(&flg->ndefer, 1u)] = p;
-      continue;
+  } else {
+    const int tor[3] = {org[0], org[1], torg2};
+    // the cell relative to the tile (periodic fold); false outside the
+    // tile's drift allowance
+    auto locate = [&](const int* c3, int* l) {
+      bool fast = true;
+#pragma unroll
+      for (int d = 0; d < DIMS; ++d) {
+        const int Td = d == 2 ? G::B::TZ : G::T;
+        const int Ad = d == 2 ? G::AZ : G::A;
+        int v = c3[d] - tor[d];
+        if (P.bc[d] == PIC_BC_PERIODIC) {
+          v = v < 0 ? v + P.n[d] : v;
+          if (v >= Td + Ad) v -= P.n[d];
+        }
+        l[d] = v;
+        fast = fast && v >= -Ad && v < Td + Ad;
+      }
+      return fast;
+    };
+    // Every slab scans all of the tile's particles, a slab's share is about
+    // 1/S of them: each wavefront queues the indices of its slab's particles
+    // (allowance cells below and above the tile go to the end slabs) and
+    // runs whole 64-lane batches from the queue's end (at most 63 wait when
+    // 64 more arrive, so 128 entries suffice).
+    __shared__ int s_own[G::NT / 64][G::QCAP];
+    const int lane = threadIdx.x & 63;
+    int* q = s_own[threadIdx.x >> 6];
+    int qn = 0;  // uniform over the wavefront
+    for (int b = pbeg + (threadIdx.x & ~63);; b += G::NT) {
+      const bool more = b < pend;
+      if (more) {
+        const int p = b + lane;
+        bool own = false;
+        if (p < pend) {
+          const PState<R> s = load_particle<DIMS, R>(pa, p, P.q_const);
+          int c3[3] = {0, 0, 0};
+          if (s.cl >= 0 && decode<DIMS, R>(P, s, c3, flg)) {
+            int l[3] = {0, 0, 0};
+            if (!locate(c3, l)) {
+              if (slab == 0) deferred[atomicAdd(&flg->ndefer, 1u)] = p;
+            } else {
+              own = (l[2] < 0 ? 0 : (l[2] / G::TZ < S ? l[2] / G::TZ : S - 1)) == slab;
+            }
+          }
+        }
+        const unsigned long long m = __ballot(own);
+        if (own) q[qn + (int)__popcll(m & ((1ull << lane) - 1ull))] = p;
+        qn += (int)__popcll(m);
+      }
+      if (qn >= 64 || (!more && qn > 0)) {
+        __builtin_amdgcn_wave_barrier();
+        const int cnt = qn < 64 ? qn : 64;
+        const int p = lane < cnt ? q[qn - cnt + lane] : -1;
+        __builtin_amdgcn_wave_barrier();
+        qn -= cnt;
+        if (p >= 0) {
+          PState<R> s = load_particle<DIMS, R>(pa, p, P.q_const);
+          int c3[3] = {0, 0, 0};
+          decode<DIMS, R>(P, s, c3, flg);
+          int l[3] = {0, 0, 0};
+          locate(c3, l);
+          l[2] -= slab * G::TZ;
+          LdsFields<DIMS, ORDER, R, G> acc{(lds_ptr<const R>)s_eb,
+                                           ((l[2] - G::e_lo_z) * G::ex + (l[1] - G::e_lo)) * G::ex +
+                                               (l[0] - G::e_lo)};
+          const PState<R> s0 = s;
+          FwdPart<R> f;
+          if (forward_part<DIMS, ORDER, R>(P, acc, s, f, flg)) {
+            if (!f.small)
+              deferred[atomicAdd(&flg->ndefer, 1u)] = p;
+            else
+              adjoint_part<DIMS, ORDER, R>(P, ac, l, s0, s, f, lam, p);
+          }
+        }
+      }
+      if (!more) break;
     }
-    if (S > 1) {  // the slab of the particle's cell (allowance cells go to the end slabs)
-      const int k = l[2] < 0 ? 0 : (l[2] / G::TZ < S ? l[2] / G::TZ : S - 1);
-      if (k != slab) continue;
-      l[2] -= slab * G::TZ;
-    }
-    LdsFields<DIMS, ORDER, R, G> acc{
-        (lds_ptr<const R>)s_eb, ((l[2] - G::e_lo_z) * G::ex + (l[1] - G::e_lo)) * G::ex + (l[0] - G::e_lo)};
-    const PState<R> s0 = s;
-    FwdPart<R> f;
-    if (!forward_part<DIMS, ORDER, R>(P, acc, s, f, flg)) continue;
-    if (!f.small) {
-      deferred[atomicAdd(&flg->ndefer, 1u)] = p;
-      continue;
-    }
-    adjoint_part<DIMS, ORDER, R>(P, ac, l, s0, s, f, lam, p);
   }
   __syncthreads();
   // lamE, lamB of the region (its halo overlaps the neighbouring regions')
