@@ -187,6 +187,46 @@ def run_window(w, real_bytes, shifts, log):
             "shifts_per_step": round(wo.dt / wo.dx3[0], 4)}
 
 
+def run_adjoint(w, real_bytes, reps, log):
+    """One step's push/deposit adjoint (pic_push_deposit_adjoint) on workload
+    w after a sort: with the sort's workspace (LDS kernel per tile in 2D, per
+    z slab of a tile in 3D, where the form fits) and with a workspace holding
+    no tile bins (one thread per particle in global memory).  Random adjoint
+    inputs; ms per call, mean of `reps` calls after one untimed call."""
+    import torch
+    from paper_1310_0930_amd import pic as P
+    pl = I.make_plasma(w)
+    E, B = I.laser_fields(w)
+    sim = P.Simulation.from_workload(w, real_bytes=real_bytes)
+    sim.load(pl, E, B, with_id=False)
+    del pl
+    sim.sort()
+    g = torch.Generator(device=sim.device).manual_seed(1310)
+    LJ = torch.randn(sim.J.shape, generator=g, device=sim.device, dtype=sim.real)
+    LX = torch.randn(sim.off.shape, generator=g, device=sim.device, dtype=sim.real)
+    LU = torch.randn(sim.u.shape, generator=g, device=sim.device, dtype=sim.real)
+    LE, LB = torch.zeros_like(sim.E), torch.zeros_like(sim.B)
+    lam_f = P.fields_struct(LE, LB, LJ)
+    lam_p = P.particles_struct(sim.np, None, LX, LU)
+    res = {}
+    for tag, ws in (("lds", sim.ws), ("global", torch.zeros_like(sim.ws))):
+        P.pic_push_deposit_adjoint(sim.ctx, sim._parts, sim._fields, lam_f, lam_p, ws.data_ptr(),
+                                   sim.stream)
+        torch.cuda.synchronize()
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0.record()
+        for _ in range(reps):
+            P.pic_push_deposit_adjoint(sim.ctx, sim._parts, sim._fields, lam_f, lam_p,
+                                       ws.data_ptr(), sim.stream)
+        t1.record()
+        torch.cuda.synchronize()
+        res[tag] = t0.elapsed_time(t1) / reps
+    log(f"adjoint {w.name} real={real_bytes}: {res['lds']:.3f} ms per step adjoint "
+        f"(global-memory kernel {res['global']:.3f} ms)")
+    return {"ms": round(res["lds"], 4), "pushes_per_s": sim.np / (res["lds"] * 1e-3),
+            "global_memory_kernel_ms": round(res["global"], 4), "particles": sim.np}
+
+
 def cpu_baseline(w, log, budget_s=12.0):
     """The FP64 oracle (as it stands) on the host cores: one push/deposit pass
     over a bounded prefix of the workload's particles plus one full-grid FDTD
@@ -235,6 +275,8 @@ def main():
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--window", type=int, default=0, metavar="K",
                     help="also time K moving-window shifts on the workload's grid (x made open)")
+    ap.add_argument("--adjoint", type=int, default=0, metavar="K",
+                    help="also time K calls of one step's push/deposit adjoint after a sort")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 1 GiB device-to-device copy (for scaling the "
                          "rocprofv3 FETCH_SIZE/WRITE_SIZE counters)")
@@ -299,6 +341,10 @@ def main():
         out["window_shift"] = {"f32": run_window(w, 4, a.window, log)}
         if not a.no_fp64:
             out["window_shift"]["f64"] = run_window(w, 8, a.window, log)
+    if a.adjoint > 0:
+        out["step_adjoint"] = {"f32": run_adjoint(w, 4, a.adjoint, log)}
+        if not a.no_fp64:
+            out["step_adjoint"]["f64"] = run_adjoint(w, 8, a.adjoint, log)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, log)
     t3 = json.load(open(os.path.join(ROOT, "tests", "golden", "paper_table3.json")))
