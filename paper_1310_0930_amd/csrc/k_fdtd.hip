@@ -5,7 +5,9 @@
 // communication volume (Sec. 3).  C is the forward-difference curl of E at
 // the B positions and C^T (its transpose) the backward-difference curl of B
 // at the E positions.  One thread per cell updates the three components;
-// reads of the neighbours along x are coalesced and the rest hit L2.
+// reads of the neighbours along x are coalesced and the rest hit L2.  On 3D
+// grids periodic along every axis one thread takes a short z column instead
+// (k_half_b_col, k_advance_e_col).
 //
 // Open faces: the tangential E samples on the first and last node planes of
 // an open axis are advanced with the first-order Mur condition
@@ -161,6 +163,74 @@ __global__ void k_advance_e(FdParams P, MurPlanes M, R* __restrict__ E0, R* __re
   }
 }
 
+// The same two updates on a 3D grid with every axis periodic, one thread
+// per (i, j) column of FD_KC consecutive z planes: the column's index
+// arithmetic and wraps are formed once, and the z neighbour of one plane is
+// the next plane's centre sample, kept in registers.  Consecutive threads
+// take consecutive x, so every load and store stays coalesced.
+constexpr int FD_KC = 4;
+
+__device__ __forceinline__ int column_start(const FdParams& P, int t, int& i, int& j, int& k0) {
+  const uint32_t q0 = P.dn0.div((uint32_t)t);  // t / n0
+  i = t - (int)q0 * P.n[0];
+  const uint32_t q1 = P.dn1.div(q0);  // column block along z
+  j = (int)(q0 - q1 * P.n[1]);
+  k0 = (int)q1 * FD_KC;
+  return i + P.n[0] * (j + P.n[1] * k0);
+}
+
+// B -= h C E (forward differences)
+template <typename R>
+__global__ void k_half_b_col(FdParams P, const R* __restrict__ E0, const R* __restrict__ E1,
+                             const R* __restrict__ E2, R* __restrict__ B0, R* __restrict__ B1,
+                             R* __restrict__ B2, R hx, R hy, R hz, int ncol) {
+  const int t = xcd_block() * blockDim.x + threadIdx.x;
+  if (t >= ncol) return;
+  int i, j, k0;
+  int idx = column_start(P, t, i, j, k0);
+  const int plane = P.n[0] * P.n[1];
+  const int ip = i + 1 < P.n[0] ? 1 : 1 - P.n[0];
+  const int jp = j + 1 < P.n[1] ? P.n[0] : P.n[0] - plane;
+  R exk = E0[idx], eyk = E1[idx];  // E_x, E_y at plane k
+#pragma unroll
+  for (int kk = 0; kk < FD_KC; ++kk, idx += plane) {
+    const int kp = k0 + kk + 1 < P.n[2] ? plane : plane - P.n[2] * plane;
+    const R ex1 = E0[idx + kp], ey1 = E1[idx + kp], ez = E2[idx];
+    B0[idx] -= hy * (E2[idx + jp] - ez) - hz * (ey1 - eyk);
+    B1[idx] -= hz * (ex1 - exk) - hx * (E2[idx + ip] - ez);
+    B2[idx] -= hx * (E1[idx + ip] - eyk) - hy * (E0[idx + jp] - exk);
+    exk = ex1;
+    eyk = ey1;
+  }
+}
+
+// E += g C^T B - dt J (backward differences)
+template <typename R>
+__global__ void k_advance_e_col(FdParams P, R* __restrict__ E0, R* __restrict__ E1,
+                                R* __restrict__ E2, const R* __restrict__ B0,
+                                const R* __restrict__ B1, const R* __restrict__ B2,
+                                const R* __restrict__ J0, const R* __restrict__ J1,
+                                const R* __restrict__ J2, R gx, R gy, R gz, R dt, int ncol) {
+  const int t = xcd_block() * blockDim.x + threadIdx.x;
+  if (t >= ncol) return;
+  int i, j, k0;
+  int idx = column_start(P, t, i, j, k0);
+  const int plane = P.n[0] * P.n[1];
+  const int im = i > 0 ? -1 : P.n[0] - 1;
+  const int jm = j > 0 ? -P.n[0] : plane - P.n[0];
+  const int km = k0 > 0 ? -plane : (P.n[2] - 1) * plane;
+  R bxm = B0[idx + km], bym = B1[idx + km];  // B_x, B_y at plane k - 1
+#pragma unroll
+  for (int kk = 0; kk < FD_KC; ++kk, idx += plane) {
+    const R bx = B0[idx], by = B1[idx], bz = B2[idx];
+    E0[idx] += (gy * (bz - B2[idx + jm]) - gz * (by - bym)) - dt * J0[idx];
+    E1[idx] += (gz * (bx - bxm) - gx * (bz - B2[idx + im])) - dt * J1[idx];
+    E2[idx] += (gx * (by - B1[idx + im]) - gy * (bx - B0[idx + jm])) - dt * J2[idx];
+    bxm = bx;
+    bym = by;
+  }
+}
+
 // Mur update of the samples on the face (d, side) with exactly `pass` open
 // boundary axes, along their lowest such axis.
 template <typename R>
@@ -240,6 +310,18 @@ static int launch_fa(const pic_ctx* ctx, const pic_fields* f, void* ws, hipStrea
         M.off[d][sd][c] = off;
         if (P.open[d] && c != d) off += (long)P.n[a] * P.n[b];
       }
+  }
+  if (P.dims == 3 && !P.open[0] && !P.open[1] && !P.open[2] && P.n[2] % FD_KC == 0) {
+    const int ncol = ncell / FD_KC;
+    const unsigned cgrid = xcd_grid(ncol);  // a multiple of 8 blocks (xcd_block)
+    k_half_b_col<R><<<dim3(cgrid), dim3(256), 0, s>>>(P, E[0], E[1], E[2], B[0], B[1], B[2], h[0],
+                                                       h[1], h[2], ncol);
+    k_advance_e_col<R><<<dim3(cgrid), dim3(256), 0, s>>>(P, E[0], E[1], E[2], B[0], B[1], B[2],
+                                                          J[0], J[1], J[2], g[0], g[1], g[2], dt,
+                                                          ncol);
+    k_half_b_col<R><<<dim3(cgrid), dim3(256), 0, s>>>(P, E[0], E[1], E[2], B[0], B[1], B[2], h[0],
+                                                       h[1], h[2], ncol);
+    return (int)hipGetLastError();
   }
   const unsigned grid = xcd_grid(ncell);  // a multiple of 8 blocks (xcd_block)
   k_half_b<R><<<dim3(grid), dim3(256), 0, s>>>(P, E[0], E[1], E[2], B[0], B[1], B[2], h[0], h[1],
