@@ -32,11 +32,17 @@ def _t(a, sim):
     return torch.from_numpy(np.ascontiguousarray(a)).to(sim.device, sim.real)
 
 
-@pytest.mark.parametrize("dims,bc,rb", [(3, (0, 0, 0), 8), (2, (0, 1), 8), (3, (0, 1, 1), 8),
-                                        (2, (1, 1), 8), (3, (0, 1, 1), 4)])
-def test_field_advance_adjoint_dot_product(dims, bc, rb):
+@pytest.mark.parametrize("dims,bc,rb,nz", [(3, (0, 0, 0), 8, 9), (3, (0, 0, 0), 8, 8),
+                                           (3, (0, 0, 0), 4, 8), (2, (0, 1), 8, 0),
+                                           (3, (0, 1, 1), 8, 9), (2, (1, 1), 8, 0),
+                                           (3, (0, 1, 1), 4, 9)])
+def test_field_advance_adjoint_dot_product(dims, bc, rb, nz):
+    """<lamE, E'> + <lamB, B'> of one field advance equals the adjoint's
+    <lamE', dE> + <lamB', dB> + <lamJ', dJ>.  nz = 8 on a periodic 3D grid
+    takes the z-column kernels of the forward advance, nz = 9 the
+    one-thread-per-cell ones."""
     from paper_1310_0930_amd import pic as P
-    n = (12, 10, 9) if dims == 3 else (16, 12)
+    n = (12, 10, nz) if dims == 3 else (16, 12)
     dx = (0.2, 0.25, 0.3)[:dims]
     w = I.Workload("fa", dims, n, dx, 2, 1, 0.0, 1, bc=bc)
     sim = _sim(w, rb)
