@@ -227,6 +227,54 @@ def test_fdtd_eigenmode_fp64():
     np.testing.assert_allclose(st["E"][2, 0], np.cos(kx * x + ky * y - om * 100 * dt), atol=1e-11)
 
 
+def test_fdtd_eigenmode_3d_oblique_fp64():
+    """An oblique vacuum Yee eigenmode on a periodic 3D grid (nz = 8: the
+    z-column kernels of the field advance) equals the closed form: with the
+    discrete wave vector kt_d = 2 sin(k_d dx_d / 2) / dx_d and frequency
+    sin(w dt / 2) = |kt| dt / 2, E = E0 cos(k.r_E - w t) with kt.E0 = 0 and B
+    = (kt x E0) / |kt| cos(k.r_B - w t) at every staggered sample."""
+    from paper_1310_0930_amd.pic import Simulation
+    n = (16, 12, 8)
+    dx = (0.2, 0.25, 0.3)
+    dt = 0.9 / np.sqrt(sum(1 / d ** 2 for d in dx))
+    k = np.array([2 * np.pi * m / (nn * d) for m, nn, d in zip((2, 1, 1), n, dx)])
+    kt = 2 * np.sin(k * np.array(dx) / 2) / np.array(dx)
+    wt = np.linalg.norm(kt)
+    om = 2 / dt * np.arcsin(wt * dt / 2)
+    E0 = np.cross(kt, [0.3, -0.5, 1.0])  # all three components nonzero
+    E0 /= np.linalg.norm(E0)
+    B0 = np.cross(kt, E0) / wt
+    kk, jj, ii = np.meshgrid(np.arange(n[2]), np.arange(n[1]), np.arange(n[0]), indexing="ij")
+    L = [ii, jj, kk]
+
+    def phase(c, stag_b, t):
+        # sample c of E (stagger along c) or of B (stagger along the other two)
+        ph = 0.0
+        for d in range(3):
+            half = (d != c) if stag_b else (d == c)
+            ph = ph + k[d] * (L[d] + 0.5 * half) * dx[d]
+        return ph - om * t
+
+    c = O.Config(3, n, dx, dt, 1)
+    E = c.zeros_field()
+    B = c.zeros_field()
+    for comp in range(3):
+        E[comp] = E0[comp] * np.cos(phase(comp, False, 0.0))
+        B[comp] = B0[comp] * np.cos(phase(comp, True, -dt / 2))
+    B -= 0.5 * dt * O.curl_e(c, E)  # B at integer time 0, as the step keeps it
+    sim = Simulation(3, n, dx, dt, 1, real_bytes=8)
+    empty = I.Plasma(np.zeros(0, np.int32), np.zeros((3, 0), np.float32),
+                     np.zeros((3, 0), np.float32), None, -1.0)
+    sim.load(empty, E, B, with_id=False)
+    steps = 60
+    for _ in range(steps):
+        sim.field_advance()
+    st = sim.download()
+    for comp in range(3):
+        np.testing.assert_allclose(st["E"][comp], E0[comp] * np.cos(phase(comp, False, steps * dt)),
+                                   atol=1e-11)
+
+
 # ---------------------------------------------------------------- edge cases
 def _tile_geometry(dims, order, rb):
     """Tile sizes and the push kernel's LDS field-region strides for a
