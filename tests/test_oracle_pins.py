@@ -319,6 +319,30 @@ def test_mur_absorbs_at_half_courant():
     assert s.energies()[0] < 1e-3 * w0
 
 
+def test_mur_absorbs_at_the_edges_of_two_open_faces():
+    """3D, y and z open (x periodic): an E_x pulse (uniform in x, so
+    divergence free, B = 0 at t = 0) splits into two packets that run along
+    the (y+z) diagonal into the two y-z edges of the box, where every E_x
+    sample lies on two open faces.  At half the Courant limit first-order
+    Mur absorbs them: after both packets have crossed the edges, less than
+    2e-3 of the energy is left (without an update of the edge samples they
+    stay at zero and reflect about 2e-2)."""
+    ny = nz = 48
+    d = 0.2
+    c = cfg3(n=(4, ny, nz), dx=(d, d, d), order=1, bc=(0, OPEN_, OPEN_))
+    k, j, _ = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(4), indexing="ij")
+    yc = zc = (ny - 1) * d / 2
+    xi = ((j * d - yc) + (k * d - zc)) / math.sqrt(2)
+    eta = ((k * d - zc) - (j * d - yc)) / math.sqrt(2)
+    E = c.zeros_field()
+    E[0] = np.exp(-(xi / 0.6) ** 2 - (eta / 1.0) ** 2)
+    s = O.State(c, np.zeros((0, 3)), np.zeros((0, 3)), np.zeros(0), E, c.zeros_field())
+    w0 = s.energies()[0]
+    for _ in range(int(15.0 / c.dt)):
+        s.field_advance()
+    assert s.energies()[0] < 2e-3 * w0
+
+
 # ---------------------------------------------------------------- deposit
 def _random_paths(c, m, maxmove=0.45):
     D = c.dims
@@ -429,6 +453,86 @@ def test_deposit_2d_out_of_plane_current():
     X1 = X + np.array([[0.4, -0.3, 0.0]])
     J = O.deposit_paths(c, X, X1, 0.5, vz=0.7)
     assert abs(J[2].sum() - 0.35) < 1e-14
+
+
+def _hat_integral_2d(X0, X1, i, j):
+    """Exact integral over t in [0, 1] of hat(x(t) - i) hat(y(t) - j) along the
+    straight path X0 -> X1: between the crossings of integer planes each hat
+    is linear in t, so the product is quadratic and Simpson's rule on every
+    such piece is exact."""
+    cuts = [0.0, 1.0]
+    for d in range(2):
+        a, b = X0[d], X1[d]
+        if b != a:
+            for m in range(int(np.floor(min(a, b))) + 1, int(np.ceil(max(a, b)))):
+                t = (m - a) / (b - a)
+                if 0.0 < t < 1.0:
+                    cuts.append(t)
+    cuts = np.sort(np.array(cuts))
+    hat = lambda v: max(0.0, 1.0 - abs(v))  # noqa: E731
+
+    def f(t):
+        return hat(X0[0] + t * (X1[0] - X0[0]) - i) * hat(X0[1] + t * (X1[1] - X0[1]) - j)
+
+    tot = 0.0
+    for ta, tb in zip(cuts[:-1], cuts[1:]):
+        tot += (tb - ta) / 6.0 * (f(ta) + 4.0 * f(0.5 * (ta + tb)) + f(tb))
+    return tot
+
+
+def test_deposit_2d_out_of_plane_current_is_the_time_integral_at_order_1():
+    """2D3V, order 1: the charge-conserving J_z of a path is the exact time
+    average of the particle's charge cloud times q v_z,
+    J_z(i, j) = q v_z * integral_0^1 hat(x(t) - i) hat(y(t) - j) dt,
+    on paths inside one cell and on paths that cross one or two cell faces
+    (virtual segments, Sec. 5.2).  Pins the 1/2 S0 dS and 1/3 dS dS cross
+    terms of the out-of-plane deposit, which the at-rest case cannot see."""
+    c = cfg2(n=(12, 10), order=1)
+    ncross = 0
+    for trial in range(40):
+        X0 = np.zeros((1, 3))
+        X0[0, :2] = RNG.uniform(3.0, 7.0, size=2)
+        X1 = X0.copy()
+        X1[0, :2] += RNG.uniform(-0.45, 0.45, size=2)
+        if trial < 6:  # paths inside one cell
+            X1[0, :2] = np.floor(X0[0, :2]) + RNG.uniform(0.0, 1.0, size=2)
+        ncross += int(np.any(np.floor(X0[0, :2]) != np.floor(X1[0, :2])))
+        q, vz = RNG.uniform(-1.0, 1.0), RNG.normal()
+        J = O.deposit_paths(c, X0, X1, q, vz=vz)
+        ref = np.zeros(c.shape[1:])
+        lo = np.floor(np.minimum(X0[0], X1[0])).astype(int)
+        for j in range(lo[1], lo[1] + 3):
+            for i in range(lo[0], lo[0] + 3):
+                ref[j, i] = q * vz * _hat_integral_2d(X0[0], X1[0], i, j)
+        np.testing.assert_allclose(J[2, 0], ref, rtol=0, atol=1e-14 * max(1.0, abs(q * vz)))
+    assert ncross >= 8
+
+
+@pytest.mark.parametrize("order", [1, 2, 3, 4])
+def test_deposit_2d_out_of_plane_current_moments(order):
+    """2D3V at every order: with the time-linear shape of each virtual
+    segment the out-of-plane current carries the path's moments exactly.
+    B-spline weights have unit mass and first moment equal to the position,
+    so sum J_z = q v_z, sum i J_z = q v_z (x0 + x1)/2 (likewise in y) and
+    sum i j J_z = q v_z * integral_0^1 x(t) y(t) dt
+    = q v_z (x0 y0 + (dx y0 + x0 dy)/2 + dx dy / 3) for the straight path."""
+    c = cfg2(n=(20, 18), order=order)
+    ii, jj = np.meshgrid(np.arange(20), np.arange(18), indexing="xy")
+    for _ in range(30):
+        X0 = np.zeros((1, 3))
+        X0[0, :2] = RNG.uniform(6.0, 11.0, size=2)
+        X1 = X0.copy()
+        X1[0, :2] += RNG.uniform(-0.45, 0.45, size=2)
+        q, vz = RNG.uniform(0.2, 1.0), RNG.uniform(0.2, 1.0)
+        Jz = O.deposit_paths(c, X0, X1, q, vz=vz)[2, 0]
+        (x0, y0), (x1, y1) = X0[0, :2], X1[0, :2]
+        dxp, dyp = x1 - x0, y1 - y0
+        qv = q * vz
+        assert abs(Jz.sum() - qv) < 1e-13
+        assert abs((ii * Jz).sum() - qv * 0.5 * (x0 + x1)) < 1e-12
+        assert abs((jj * Jz).sum() - qv * 0.5 * (y0 + y1)) < 1e-12
+        xy = x0 * y0 + 0.5 * (dxp * y0 + x0 * dyp) + dxp * dyp / 3.0
+        assert abs((ii * jj * Jz).sum() - qv * xy) < 1e-11
 
 
 # ---------------------------------------------------------------- whole step
@@ -636,6 +740,30 @@ def test_two_species_continuity_and_gauss(dims):
 
 
 
+def test_kinetic_energy_limits():
+    """W_kin = sum m_p dV (gamma - 1): exactly zero for a cold plasma, and
+    for slow particles the series gamma - 1 = u^2/2 - u^4/8 + O(u^6): the
+    Newtonian 1/2 sum m_p u^2 dV plus its first relativistic correction
+    (u ~ 1e-3: the next term is 1e-12 relative); m_p = |q_p| / |q/m|."""
+    c = cfg2(n=(8, 8), order=2)
+    m = 500
+    X = np.zeros((m, 3))
+    X[:, :2] = RNG.uniform(0.0, 8.0, size=(m, 2))
+    q = -RNG.uniform(0.1, 1.0, size=m)
+    dV = c.dx[0] * c.dx[1]
+    s = O.State(c, X, np.zeros((m, 3)), q, c.zeros_field(), c.zeros_field())
+    assert s.energies()[1] == 0.0
+    u = RNG.normal(0.0, 1e-3, size=(m, 3))
+    s = O.State(c, X, u, q, c.zeros_field(), c.zeros_field())
+    u2 = np.sum(u ** 2, axis=1)
+    newton = dV * np.sum(np.abs(q) * (0.5 * u2 - 0.125 * u2 ** 2))
+    assert abs(s.energies()[1] / newton - 1.0) < 1e-8
+    # ions (q/m = 1/M) weigh M times their charge
+    ci = O.Config(c.dims, c.n, c.dx, c.dt, c.order, c.bc, q_over_m=1.0 / 25.0)
+    si = O.State(ci, X, u, -q, c.zeros_field(), c.zeros_field())
+    assert abs(si.energies()[1] / (25.0 * newton) - 1.0) < 1e-8
+
+
 # ---------------------------------------------------------------- moving window, antenna
 def test_discrete_poynting_identity_with_antenna():
     """With B kept at integer times by two half steps, W~ = 1/2 (|E|^2 + |B|^2)
@@ -682,6 +810,34 @@ def test_antenna_emits_the_requested_field():
         trace.append(s.E[1, 0, 0, probe])
     peak = np.max(np.abs(trace))
     assert abs(peak / (a.a0 * a.omega0) - 1.0) < 1e-2
+
+
+def test_antenna_field_sign_and_phase():
+    """The signed field of the antenna: at distance r on either side the
+    sheet's field is E_y(t) = a0 omega0 env(t - r) cos(omega0 (t - r - t_c))
+    (E = -K/2 with K = -2 a0 omega0 env cos), sample by sample within 1 % of
+    the peak (a current of the opposite sign would be off by twice the peak)."""
+    n0 = 400
+    c = O.Config(2, (n0, 4, 1), (0.05, 0.2, 1.0), 0.5 * 0.05, 2, (OPEN_, 0, 0))
+    a = O.Antenna(x_index=200, polarization=1, a0=0.3, omega0=2.0, waist=1e9, tau=2.0,
+                  t_center=6.0, y_center=0.0)
+    s = O.State(c, np.zeros((0, 3)), np.zeros((0, 3)), np.zeros(0), c.zeros_field(),
+                c.zeros_field())
+    s.antenna = a
+    probes = (230, 170)
+    traces = {p: [] for p in probes}
+    ts = []
+    for n in range(int(14.0 / c.dt)):
+        s.step(1)
+        ts.append((n + 1) * c.dt)
+        for p in probes:
+            traces[p].append(s.E[1, 0, 0, p])
+    ts = np.array(ts)
+    amp = a.a0 * a.omega0
+    for p in probes:
+        tr = ts - abs(p - a.x_index) * c.dx[0] - a.t_center
+        ref = amp * np.exp(-tr ** 2 / a.tau ** 2) * np.cos(a.omega0 * tr) * (np.abs(tr) <= 3 * a.tau)
+        assert np.abs(np.array(traces[p]) - ref).max() < 1e-2 * amp
 
 
 @pytest.mark.parametrize("dims", [2, 3])
