@@ -41,23 +41,55 @@ def algorithmic_bytes(w, np_, real_bytes):
     return np_ * per_particle + w.ncell * per_cell * nspecies
 
 
-# Conflict-free LDS atomic rates of this chip (G lane-ops/s, whole GPU), from
-# a microbenchmark of ds_add_u64 and ds_add_f64 over 16 waves per CU.
-LDS_ATOMIC_PEAK = {4: 3714.0, 8: 3423.0}
+# LDS probe (liblds_probe.so): lane-operations per second of one LDS access
+# kind with the 64 lanes of every wavefront `stride` elements apart.
+PROBE_OPS = {"ds_read_b32": 0, "ds_read_b64": 1, "ds_add_u32": 2, "ds_add_u64": 3,
+             "ds_add_f32": 4, "ds_add_f64": 5}
+_PROBE = None
+
+
+def lds_rate(op, stride=1, iters=2048, reps=3):
+    """Whole-chip rate of LDS op `op` (G lane-ops/s, best of `reps` runs of
+    8 workgroups of 1024 threads per compute unit)."""
+    import ctypes as C
+    import torch
+    from paper_1310_0930_amd import build as B
+    global _PROBE
+    if _PROBE is None:
+        _PROBE = (C.CDLL(B.PROBE_LIB), torch.zeros(1, dtype=torch.int64, device="cuda"))
+    lib, sink = _PROBE
+    blocks = 8 * torch.cuda.get_device_properties(0).multi_processor_count
+    ms = C.c_float()
+    best = float("inf")
+    stream = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    for _ in range(reps):
+        st = lib.lds_probe_run(PROBE_OPS[op], int(stride), int(iters), blocks,
+                               C.c_void_p(sink.data_ptr()), stream, C.byref(ms))
+        if st != 0:
+            raise RuntimeError(f"lds_probe_run({op}, {stride}) failed: {st}")
+        best = min(best, ms.value)
+    return blocks * 1024 * iters / (best * 1e-3) / 1e9
+
+
+def lds_probe_table(strides=(1, 2, 4, 8, 16, 32, 64, 128)):
+    return {op: {str(s): round(lds_rate(op, s), 1) for s in strides} for op in PROBE_OPS}
 
 
 def lds_atomics(w, np_, push_ms, real_bytes):
     """LDS atomic throughput of the push/deposit tile kernel against the
-    conflict-free rate: the Esirkepov current of each particle's first virtual
+    conflict-free rate of the same instruction, measured in this run by the
+    LDS probe: the Esirkepov current of each particle's first virtual
     segment adds 3 n (n+1)^2 samples in 3D and 2 n (n+1) + (n+1)^2 in 2D3V (a
     lower bound: the few particles that cross a stencil plane add more)."""
     n = w.order
     per = 3 * n * (n + 1) ** 2 if w.dims == 3 else 2 * n * (n + 1) + (n + 1) ** 2
     ops = per * np_
     ach = ops / (push_ms * 1e-3) / 1e9
-    peak = LDS_ATOMIC_PEAK[real_bytes]
-    return {"op": "ds_add_u64 (exact fixed point)" if real_bytes == 4 else "ds_add_f64",
+    op = "ds_add_u64" if real_bytes == 4 else "ds_add_f64"
+    peak = round(lds_rate(op), 1)
+    return {"op": op + (" (exact fixed point)" if real_bytes == 4 else ""),
             "lane_ops_per_launch": int(ops), "achieved": round(ach, 1), "peak": peak,
+            "peak_source": "LDS probe in this run: conflict-free, 8 x 1024-thread workgroups per CU",
             "unit": "G lane-ops/s", "frac": round(ach / peak, 4)}
 
 
@@ -80,11 +112,22 @@ def traffic_from_profile(workload, real):
     return rec.get("traffic_bytes")
 
 
+_INPUTS = {}
+
+
+def workload_inputs(w):
+    """Seeded particles and fields of workload w (drawn once, kept for the
+    FP32 and the FP64 run)."""
+    if w.name not in _INPUTS:
+        _INPUTS.clear()
+        _INPUTS[w.name] = (I.make_plasma(w),) + tuple(I.laser_fields(w))
+    return _INPUTS[w.name]
+
+
 def run_gpu(w, real_bytes, steps, warmup, log):
     import torch
     from paper_1310_0930_amd.pic import Simulation
-    pl = I.make_plasma(w)
-    E, B = I.laser_fields(w)
+    pl, E, B = workload_inputs(w)
     sim = Simulation.from_workload(w, real_bytes=real_bytes)
     sim.load(pl, E, B, with_id=False)
     del pl
@@ -227,41 +270,64 @@ def run_adjoint(w, real_bytes, reps, log):
             "global_memory_kernel_ms": round(res["global"], 4), "particles": sim.np}
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(w, log, budget_s=12.0):
     """The FP64 oracle (as it stands) on the host cores: one push/deposit pass
     over a bounded prefix of the workload's particles plus one full-grid FDTD
-    advance, scaled to pushes per second."""
+    advance, scaled to pushes per second; once on one thread and once on
+    every thread this process may use (the CPU share of one GPU: the
+    affinity mask, capped by OMP_NUM_THREADS when that is set)."""
     import oracle as O
-    threads = max(1, min(16, os.cpu_count() or 1))
+    visible = os.cpu_count() or 1
+    allowed = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else visible
+    threads = allowed
+    if os.environ.get("OMP_NUM_THREADS", "").isdigit():
+        threads = max(1, min(threads, int(os.environ["OMP_NUM_THREADS"])))
     pl = I.make_plasma(w, slabs=range(min(8, w.particle_cells()[2 if w.dims == 3 else 1])))
     E, B = I.laser_fields(w)
     c = O.Config(w.dims, w.n3, w.dx3, w.dt, w.order, w.bc3)
     X = pl.global_positions(w)
     u = pl.u.T.astype(np.float64)
     q = pl.charges()
-    # calibrate on a small prefix, then size the sample to the time budget
-    m0 = min(pl.np, 20000)
-    s = O.State(c, X[:m0], u[:m0], q[:m0], E, B)
-    t = time.perf_counter()
-    s.push_deposit(nthreads=threads)
-    per = (time.perf_counter() - t) / m0
-    m = int(min(pl.np, max(m0, budget_s * 0.8 / max(per, 1e-9))))
-    s = O.State(c, X[:m], u[:m], q[:m], E, B)
-    t = time.perf_counter()
-    s.push_deposit(nthreads=threads)
-    t_push = time.perf_counter() - t
+
+    def timed(nthreads, budget):
+        # calibrate on a small prefix, then size the sample to the time budget
+        m0 = min(pl.np, 20000)
+        s = O.State(c, X[:m0], u[:m0], q[:m0], E, B)
+        t = time.perf_counter()
+        s.push_deposit(nthreads=nthreads)
+        per = (time.perf_counter() - t) / m0
+        m = int(min(pl.np, max(m0, budget * 0.8 / max(per, 1e-9))))
+        s = O.State(c, X[:m], u[:m], q[:m], E, B)
+        t = time.perf_counter()
+        s.push_deposit(nthreads=nthreads)
+        return m, time.perf_counter() - t, s
+
+    m1, t1, _ = timed(1, 0.35 * budget_s)
+    m, t_push, s = timed(threads, 0.65 * budget_s)
     t = time.perf_counter()
     s.field_advance()
     t_fdtd = time.perf_counter() - t
     # one whole step of the full workload would take N*t_push/m + t_fdtd
     step_s = w.num_particles * t_push / m + t_fdtd
-    log(f"cpu oracle: {m} pushes in {t_push:.2f} s on {threads} threads, fdtd {t_fdtd:.2f} s")
+    log(f"cpu oracle ({cpu_model()}, {visible} visible / {allowed} allowed cpus): {m} pushes in "
+        f"{t_push:.2f} s on {threads} threads, {m1} in {t1:.2f} s on 1 thread, fdtd {t_fdtd:.2f} s")
     return {"value": w.num_particles / step_s, "unit": "particle pushes/s", "cores": threads,
             "kind": "oracle",
-            "sample": f"1 push/deposit pass over {m} particles of {w.name} plus 1 full-grid FDTD "
-                      f"advance, FP64, {threads} threads; scaled to whole steps of "
-                      f"{w.num_particles} particles",
-            "push_only_value": m / t_push}
+            "sample": f"1 push/deposit pass over {m} particles of {w.name} on {threads} threads "
+                      f"(and over {m1} on 1 thread) plus 1 full-grid FDTD advance, FP64; scaled to "
+                      f"whole steps of {w.num_particles} particles",
+            "push_only_value": m / t_push, "per_core_push_value": m1 / t1,
+            "cpu_model": cpu_model(), "cpus_visible": visible, "cpus_allowed": allowed}
 
 
 def main():
@@ -277,6 +343,12 @@ def main():
                     help="also time K moving-window shifts on the workload's grid (x made open)")
     ap.add_argument("--adjoint", type=int, default=0, metavar="K",
                     help="also time K calls of one step's push/deposit adjoint after a sort")
+    ap.add_argument("--share-workload", default="w3d_512_quadratic_laser",
+                    choices=sorted(I.WORKLOADS) + ["none"],
+                    help="second record: the one-GPU share of an LWFA run (FP32 and FP64)")
+    ap.add_argument("--share-steps", type=int, default=10)
+    ap.add_argument("--lds-probe", action="store_true",
+                    help="also report the LDS probe's rates for every access kind and lane stride")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 1 GiB device-to-device copy (for scaling the "
                          "rocprofv3 FETCH_SIZE/WRITE_SIZE counters)")
@@ -337,6 +409,32 @@ def main():
                        "roofline": roof(r64, 8, "f64"),
                        "lds_atomics": lds_atomics(w, r64["np"], r64["push_ms_mean"], 8),
                        "device_flags": r64["flags"]}
+    if a.share_workload != "none" and a.share_workload != w.name:
+        ws_ = I.WORKLOADS[a.share_workload]
+        k5 = max(1, a.share_steps)
+        s32 = run_gpu(ws_, 4, k5, 3, log)
+        s64 = None if a.no_fp64 else run_gpu(ws_, 8, k5, 3, log)
+        rec = {"workload": ws_.name, "grid": list(ws_.n3), "dx": list(ws_.dx3), "ppc": ws_.ppc,
+               "order": ws_.order, "particles": s32["np"], "dt": ws_.dt,
+               "sort_every": ws_.sort_every, "steps": k5, "warmup": 3}
+
+        def share(r, rb):
+            ab = algorithmic_bytes(ws_, r["np"], rb)
+            return {"value": r["np"] / (r["ms_per_step"] * 1e-3),
+                    "ms_per_step": round(r["ms_per_step"], 5),
+                    "push_deposit_pushes_per_s": r["np"] / (r["push_ms_mean"] * 1e-3),
+                    "push_ms": round(r["push_ms_mean"], 5),
+                    "roofline": {"bound": "hbm", "achieved": round(ab / (r["push_ms_mean"] * 1e-3) / 1e9, 2),
+                                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                 "frac": round(ab / (r["push_ms_mean"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                                 "alg_bytes_per_launch": ab},
+                    "slowpath_pushes": r["slowpath"], "device_flags": r["flags"]}
+        rec["f32"] = share(s32, 4)
+        if s64:
+            rec["f64"] = share(s64, 8)
+        out["one_gpu_share"] = rec
+    if a.lds_probe:
+        out["lds_probe"] = {"unit": "G lane-ops/s", "rates_by_stride": lds_probe_table()}
     if a.window > 0:
         out["window_shift"] = {"f32": run_window(w, 4, a.window, log)}
         if not a.no_fp64:

@@ -90,7 +90,8 @@ typedef struct {
 } pic_config;
 
 typedef struct {
-  int64_t np;     /* particle slots in use (absorbed particles keep their slot) */
+  int64_t np;     /* particle slots in use; absorbed particles keep their slot until
+                     pic_sort compacts them away (np then drops to the live count) */
   int32_t* cell;  /* linear index i+n0*(j+n1*k) of the cell's lower node; -1 = absorbed */
   void* off[3];   /* real offsets in [0,1) from that node, in cell units (off[2] unused in 2D) */
   void* u[3];     /* real momenta gamma*beta */
@@ -130,6 +131,8 @@ typedef struct {
   const void* off[3];  /* offsets in [0,1) (all dims, x included) */
   const void* u[3];    /* momenta */
   const void* q;       /* charges, required when the particles carry q, else NULL */
+  int64_t id_first;    /* id of the first appended particle (the others follow it),
+                          written when the particles carry ids */
 } pic_inject;
 
 /* Laser antenna: a sheet of current on the plane of E-samples x = x_index
@@ -156,10 +159,14 @@ int pic_destroy(pic_ctx* ctx);
 /* Bytes of device workspace needed for up to `np` particles. */
 int pic_workspace_bytes(const pic_ctx* ctx, int64_t np, size_t* bytes);
 
-/* Group the particles by tile (counting sort on the tile of `cell`, absorbed
- * particles last), permuting every SoA array (and id) in place, and record
- * the tile bins in `ws`.  Must precede pic_push_deposit.  This is the data
- * layout change that makes the deposit local; it does not change physics. */
+/* Group the particles by tile (counting sort on the tile of `cell`),
+ * permuting every SoA array (and id) in place, and record the tile bins in
+ * `ws`.  Absorbed particles (cell = -1, or a cell index out of range) are
+ * compacted away: p->np is lowered to the number of live particles, which
+ * fill slots 0 .. np-1; the contents of the slots from the new np up to the
+ * old one are unspecified.  Reading the live count back synchronises
+ * `stream`.  Must precede pic_push_deposit.  This is the data layout change
+ * that makes the deposit local; it does not change physics. */
 int pic_sort(pic_ctx* ctx, pic_particles* p, void* ws, void* stream);
 
 /* One gather + Boris push + move + split + charge-conserving deposit pass
@@ -176,7 +183,8 @@ int pic_push_deposit(pic_ctx* ctx, pic_particles* p, const pic_fields* f, void* 
 int pic_field_advance(pic_ctx* ctx, pic_fields* f, void* ws, void* stream);
 
 /* `nsteps` full steps: pic_sort when due (every sort_every steps, counted
- * per context, and before the first push), pic_push_deposit, pic_field_advance. */
+ * per context, and before the first push; p->np drops to the live count at
+ * every sort), pic_push_deposit, pic_field_advance. */
 int pic_step(pic_ctx* ctx, pic_particles* p, pic_fields* f, int32_t nsteps, void* ws,
              void* stream);
 
@@ -230,10 +238,13 @@ int pic_diagnostics_species(int32_t nspecies, pic_ctx* const* ctx, const pic_par
  * (F[i] <- F[i+1], the front plane zeroed), J is zeroed, every particle's
  * cell moves one cell down in x (those leaving at x < 0 are absorbed), and
  * `in->n` particles are appended in the front particle column (x = n0-2) from
- * `in` (their id, if p->id, continues the count from p->np).  Requires an
- * open x axis; `capacity` is the length of the particle arrays (PIC_EINVAL if
- * p->np + in->n exceeds it).  Updates p->np; the particles must be sorted
- * again before the next push.  f = NULL shifts only the particles (further
+ * `in` (ids in->id_first, in->id_first + 1, ... when p->id is not NULL).
+ * Requires an open x axis; `capacity` is the length of the particle arrays
+ * (PIC_EINVAL if p->np + in->n exceeds it).  Updates p->np; the particles
+ * must be sorted again before the next push, and that sort reclaims the
+ * slots of the particles absorbed at the back, so a window that keeps
+ * moving needs a capacity of about the live count plus one entering column
+ * per shift between sorts.  f = NULL shifts only the particles (further
  * species of a multi-species run, after the first species moved the fields). */
 int pic_window_shift(pic_ctx* ctx, pic_particles* p, int64_t capacity, pic_fields* f,
                      const pic_inject* in, void* ws, void* stream);

@@ -75,7 +75,7 @@ class Runner:
         s.E.copy_(a * self.E_unit)
         s.B.copy_(a * self.B_unit)
         s.sort()  # once; fixes the particle order for the whole rollout
-        self.perm = s.id.long().clone()  # slot -> caller index
+        self.perm = s.id[: s.np].long().clone()  # slot -> caller index (live particles)
         self.checkpoints = {}
         for n in range(self.steps):
             if n % self.every == 0:
@@ -111,7 +111,7 @@ class Runner:
             del states
         g_a0 = (lamE * self.E_unit).sum(dtype=torch.float64) + (lamB * self.B_unit).sum(dtype=torch.float64)
         g_u0 = torch.zeros_like(lamU)
-        g_u0[:, self.perm] = lamU
+        g_u0[:, self.perm] = lamU[:, : s.np]
         return g_a0, g_u0
 
 

@@ -1,7 +1,8 @@
 // Tile sort of the SoA particle arrays, in two levels: a counting sort on
 // the tile of the particle's cell (absorbed particles go to a last, dead
-// bin), then, inside every tile, a placement by (class, rank within the
-// cell and class, cell).
+// bin, which is dropped: the live particles are compacted to the front),
+// then, inside every tile, a placement by (class, rank within the cell and
+// class, cell).
 //
 // Not a step of the paper's method: it is the data layout that makes the
 // fused push/deposit local (one workgroup per tile, fields and currents in
@@ -280,18 +281,6 @@ struct PVal {
     if (A.id) const_cast<int*>(A.id)[j] = id;
   }
 };
-
-// Copy back of the dead bin (absorbed particles, in scatter order).
-template <typename R>
-__global__ void k_sort_copyback_dead(SortArrays<R> A, const int* __restrict__ dead_start, long np,
-                                     int dims) {
-  for (long i = *dead_start + blockIdx.x * (long)blockDim.x + threadIdx.x; i < np;
-       i += (long)gridDim.x * blockDim.x) {
-    PVal<R> v;
-    v.load(A, i, dims);
-    v.store(A, i, dims);
-  }
-}
 
 // In-bin order of a tile's cells.  A bin's cells hold one particle each
 // with one stencil shape, so in the push every LDS access of a wavefront is
@@ -574,8 +563,8 @@ static int launch_sort_t(const pic_ctx* ctx, const pic_particles* p, void* ws, h
   int* order = (int*)(w + L.order);
   k_sort_order<<<dim3(1), dim3(ORDER_NT), 0, s>>>(S, order);
   k_sort_place<R><<<dim3((unsigned)S.ntiles), dim3(PLACE_NT), 0, s>>>(A, S, starts, order, keys, c.dims);
-  const unsigned g2 = grid < 8192 ? grid : 8192;
-  k_sort_copyback_dead<R><<<dim3(g2), dim3(256), 0, s>>>(A, starts + S.ntiles, np, c.dims);
+  // absorbed particles (the dead bin) are not copied back: the caller lowers
+  // np to the live count, starts[ntiles]
   return (int)hipGetLastError();
 }
 

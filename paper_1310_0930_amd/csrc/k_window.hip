@@ -45,13 +45,14 @@ __global__ void k_shift_cells(int* __restrict__ cell, long np, FastDiv dn0) {
   }
 }
 
-// Append the front column's particles after the np existing ones.
+// Append the front column's particles after the np existing ones (ids
+// id_first, id_first + 1, ...).
 template <typename R>
 __global__ void k_inject(DParts<R> pa, long np, int dims, int n0, int n1, int ncy, int xcol,
                          const R* __restrict__ o0, const R* __restrict__ o1,
                          const R* __restrict__ o2, const R* __restrict__ u0,
                          const R* __restrict__ u1, const R* __restrict__ u2,
-                         const R* __restrict__ qin, long n, int ppc) {
+                         const R* __restrict__ qin, long n, int ppc, long id_first) {
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
     const long col = i / ppc;
     const int cy = (int)(col % ncy);
@@ -65,7 +66,7 @@ __global__ void k_inject(DParts<R> pa, long np, int dims, int n0, int n1, int nc
     pa.u[1][dst] = u1[i];
     pa.u[2][dst] = u2[i];
     if (pa.q) pa.q[dst] = qin[i];
-    if (pa.id) pa.id[dst] = (int32_t)dst;
+    if (pa.id) pa.id[dst] = (int32_t)(id_first + i);
   }
 }
 
@@ -133,7 +134,7 @@ static int window_t(const pic_ctx* ctx, pic_particles* p, const pic_fields* f,
     k_inject<R><<<dim3((unsigned)(g < 8192 ? g : 8192)), dim3(256), 0, s>>>(
         pa, np, c.dims, n0, n1, ncy, n0 - 2, (const R*)in->off[0], (const R*)in->off[1],
         (const R*)in->off[2], (const R*)in->u[0], (const R*)in->u[1], (const R*)in->u[2],
-        (const R*)in->q, in->n, in->ppc);
+        (const R*)in->q, in->n, in->ppc, (long)in->id_first);
   }
   return (int)hipGetLastError();
 }

@@ -235,13 +235,25 @@ int pic_sort(pic_ctx* ctx, pic_particles* p, void* ws, void* stream) {
   int v = check_particles(ctx, p);
   if (v) return v;
   if ((v = ensure_device(ctx))) return v;
+  ctx->sorted_cell = nullptr;  // bins are valid only once the sort has completed
   v = hip_status(launch_sort(ctx, p, ws, (hipStream_t)stream));
-  if (v == PIC_OK) {
-    ctx->sorted_cell = p->cell;
-    ctx->sorted_ws = ws;
-    ctx->sorted_np = p->np;
+  if (v != PIC_OK) return v;
+  if (p->np > 0) {
+    // compaction: the dead bin starts at the live count, which becomes np
+    int32_t live = 0;
+    const WsLayout L = ws_layout(ctx, p->np);
+    hipStream_t s = (hipStream_t)stream;
+    if (hipMemcpyAsync(&live, (const char*)ws + L.starts + sizeof(int32_t) * (size_t)ctx->ntiles,
+                       sizeof(live), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return PIC_EHIP;
+    if (live < 0 || live > p->np) return PIC_EHIP;
+    p->np = live;
   }
-  return v;
+  ctx->sorted_cell = p->cell;
+  ctx->sorted_ws = ws;
+  ctx->sorted_np = p->np;
+  return PIC_OK;
 }
 
 int pic_push_deposit(pic_ctx* ctx, pic_particles* p, const pic_fields* f, void* ws, void* stream) {

@@ -58,7 +58,7 @@ class PicDiag(C.Structure):
 
 class PicInject(C.Structure):
     _fields_ = [("n", C.c_int64), ("ppc", C.c_int32), ("off", C.c_void_p * 3),
-                ("u", C.c_void_p * 3), ("q", C.c_void_p)]
+                ("u", C.c_void_p * 3), ("q", C.c_void_p), ("id_first", C.c_int64)]
 
 
 class PicAntenna(C.Structure):
@@ -397,6 +397,7 @@ class Simulation:
         self.id = None
         if with_id:
             self.id = torch.arange(cap, dtype=torch.int32, device=dev)
+        self.n_ids = self.np  # ids handed out so far (injected particles continue the count)
         nbytes = pic_workspace_bytes(self.ctx, cap)
         self.ws = torch.zeros(nbytes, dtype=torch.uint8, device=dev)
         self._parts = PicParticles(
@@ -442,7 +443,10 @@ class Simulation:
         return self.torch.cuda.current_stream(self.device).cuda_stream
 
     def sort(self):
+        """Tile sort; absorbed particles are compacted away (np drops to the
+        live count)."""
         pic_sort(self.ctx, self._parts, self.ws.data_ptr(), self.stream)
+        self.np = self._parts.np
 
     def push_deposit(self):
         pic_push_deposit(self.ctx, self._parts, self._fields, self.ws.data_ptr(), self.stream)
@@ -460,6 +464,8 @@ class Simulation:
                              [s.ws.data_ptr() for s in all_], self._fields, nsteps, self.stream)
         else:
             pic_step(self.ctx, self._parts, self._fields, nsteps, self.ws.data_ptr(), self.stream)
+        for s in [self] + self.species:  # sorts inside the steps compact
+            s.np = s._parts.np
 
     def rho(self):
         """Charge density of all species (FP64, ncell)."""
@@ -508,9 +514,11 @@ class Simulation:
         q = None if plasma.q is None else torch.from_numpy(plasma.q).to(self.device, self.real)
         self._inj_keep = (off, u, q)  # alive until the stream has consumed them
         ppc = plasma.extra.get("ppc", 1)
+        first = self.n_ids
+        self.n_ids += plasma.np
         return PicInject(plasma.np, int(ppc), (C.c_void_p * 3)(*[off[d].data_ptr() for d in range(3)]),
                          (C.c_void_p * 3)(*[u[c].data_ptr() for c in range(3)]),
-                         q.data_ptr() if q is not None else None)
+                         q.data_ptr() if q is not None else None, first)
 
     def set_antenna(self, antenna):
         pic_set_antenna(self.ctx, antenna)

@@ -54,7 +54,10 @@ def compare(w, sim, ref, st=None):
     Xr = ref.X[ids]
     ur = ref.u[ids]
     alive_r = ref.alive[ids].astype(bool)
-    out = {"alive_mismatch": int(np.sum(alive_g != alive_r))}
+    # every particle the oracle still has alive is among the GPU's slots (the
+    # GPU's sort compacts absorbed particles away)
+    out = {"alive_mismatch": int(np.sum(alive_g != alive_r))
+           + abs(int(ref.alive.astype(bool).sum()) - int(alive_g.sum()))}
     both = alive_g & alive_r
     dX = Xg - Xr
     for d in range(w.dims):

@@ -294,7 +294,8 @@ def _tile_geometry(dims, order, rb):
 
 def _check_sorted(w, rb, pl, st):
     ids = st["id"]
-    assert np.array_equal(np.sort(ids), np.arange(pl.np))
+    # absorbed particles are compacted away, the live ones keep their payload
+    assert np.array_equal(np.sort(ids), np.flatnonzero(pl.cell >= 0))
     # the payload moved with its particle
     assert np.array_equal(st["cell"], pl.cell[ids])
     np.testing.assert_array_equal(st["off"], pl.off[:, ids].astype(np.float64))
@@ -346,12 +347,15 @@ def _check_sorted(w, rb, pl, st):
     return nlast
 
 
-@pytest.mark.parametrize("dims,order,rb,ppc", [(3, 2, 4, 3), (3, 2, 8, 3), (3, 3, 4, 3),
-                                               (3, 4, 8, 3), (2, 2, 4, 6), (3, 1, 4, 60)])
-def test_sort_groups_by_tile_class_and_rank_and_keeps_a_permutation(dims, order, rb, ppc):
-    """The tile sort on a shuffled ragged grid: a permutation that carries the
-    payload, tiles in order, and inside a tile the (class, rank, cell order)
-    placement; ppc = 60 puts many particles in the last rank bucket."""
+@pytest.mark.parametrize("dims,order,rb,ppc,dead", [(3, 2, 4, 3, 0.0), (3, 2, 8, 3, 0.05),
+                                                    (3, 3, 4, 3, 0.0), (3, 4, 8, 3, 0.3),
+                                                    (2, 2, 4, 6, 0.05), (3, 1, 4, 60, 0.01)])
+def test_sort_groups_by_tile_class_and_rank_and_keeps_a_permutation(dims, order, rb, ppc, dead):
+    """The tile sort on a shuffled ragged grid: a permutation of the live
+    particles that carries the payload (a fraction `dead` of absorbed
+    particles is compacted away and np drops to the live count), tiles in
+    order, and inside a tile the (class, rank, cell order) placement;
+    ppc = 60 puts many particles in the last rank bucket."""
     n = (40, 24, 16) if dims == 3 else (72, 40)
     if ppc > 10:
         n = (20, 12, 9)
@@ -362,10 +366,13 @@ def test_sort_groups_by_tile_class_and_rank_and_keeps_a_permutation(dims, order,
     perm = rng.permutation(pl.np)
     pl = I.Plasma(pl.cell[perm].copy(), pl.off[:, perm].copy(), pl.u[:, perm].copy(), None,
                   pl.q_const)
+    pl.cell[rng.random(pl.np) < dead] = -1
+    live = int(np.sum(pl.cell >= 0))
     sim = gpu_sim(w, rb, pl, E, B)
     sim.sort()
+    assert sim.np == live
     nlast = _check_sorted(w, rb, pl, sim.download())
-    say("sort", dims, order, rb, ppc, "np", pl.np, "last-bucket particles", nlast)
+    say("sort", dims, order, rb, ppc, "np", pl.np, "live", live, "last-bucket particles", nlast)
     if ppc > 10:
         assert nlast > pl.np // 4
 

@@ -24,12 +24,15 @@ def _antenna(w, a0=1.0):
                 t_center=1.5, y_center=0.5 * ny, z_center=0.5 * w.n3[2] * w.dx3[2] if w.dims == 3 else 0.0)
 
 
-def _run(w, rb, steps, antenna=None, ions=False):
+def _run(w, rb, steps, antenna=None, ions=False, spare_columns=None):
+    """Both sides through `steps` steps with the window following light.
+    The GPU's particle arrays hold np plus `spare_columns` entering columns
+    (default: every column that enters during the run)."""
     from paper_1310_0930_amd import pic as P
     pe, E, B = inputs_for(w)
     pc = w.particle_cells()
     ncol = pc[1] * (pc[2] if w.dims == 3 else 1) * w.ppc
-    nshift = int(steps * w.dt / w.dx[0]) + 1
+    nshift = int(steps * w.dt / w.dx[0]) + 1 if spare_columns is None else spare_columns
     sim = P.Simulation.from_workload(w, real_bytes=rb)
     sim.load(pe, E, B, capacity=pe.np + nshift * ncol)
     cfg = oracle_config(w)
@@ -56,7 +59,8 @@ def _run(w, rb, steps, antenna=None, ions=False):
             sim.window_shift(inj[0], species_inject=inj[1:])
             O.window_shift(ref, [(p.global_positions(w), p.u.T, p.charges()) for p in inj])
     torch.cuda.synchronize()
-    say(w.name, "real", rb, "steps", steps, "shifts", shifts, "np", sim.np)
+    say(w.name, "real", rb, "steps", steps, "shifts", shifts, "np", sim.np, "capacity",
+        sim.capacity)
     assert shifts >= 2
     return sim, ref
 
@@ -100,6 +104,25 @@ def test_moving_window_lwfa_2d(rb, steps):
     sim, ref = _run(w, rb, steps, antenna=_antenna(w))
     _check(w, rb, sim, ref, "moving window lwfa 2d")
     assert np.abs(ref.E[1]).max() > 1.0  # the pulse is there
+
+
+@pytest.mark.parametrize("rb,steps", [(8, 450), (4, 120)])
+def test_long_window_run_reuses_absorbed_slots(rb, steps):
+    """A window that keeps moving (about 200 shifts in FP64) in particle
+    arrays with room for only two entering columns: every sort compacts the
+    particles absorbed at the back, so the slots are reused and np stays
+    bounded; the state still matches the oracle particle by particle (by
+    id: the entering particles continue the id count on both sides)."""
+    w = I.Workload("winlong", 2, (64, 24), (0.1, 0.2), 2, 4, 0.02, steps, bc=(I.OPEN, I.OPEN),
+                   ramp_cells=10.0, seed=I.SEED_BASE + 128)
+    sim, ref = _run(w, rb, steps, spare_columns=2)
+    pc = w.particle_cells()
+    assert sim.np <= sim.capacity
+    assert ref.np > sim.capacity  # the oracle keeps every particle it ever had
+    assert int(sim.id[: sim.np].max()) >= ref.np - 2 * pc[1] * w.ppc
+    if rb == 8:
+        assert int(steps * w.dt / w.dx[0]) >= 200
+    _check(w, rb, sim, ref, "long window run")
 
 
 @pytest.mark.parametrize("rb", [8, 4])
