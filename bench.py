@@ -44,7 +44,7 @@ def algorithmic_bytes(w, np_, real_bytes):
 # LDS probe (liblds_probe.so): lane-operations per second of one LDS access
 # kind with the 64 lanes of every wavefront `stride` elements apart.
 PROBE_OPS = {"ds_read_b32": 0, "ds_read_b64": 1, "ds_add_u32": 2, "ds_add_u64": 3,
-             "ds_add_f32": 4, "ds_add_f64": 5}
+             "ds_add_f32": 4, "ds_add_f64": 5, "ds_read2_b32_adjacent": 6}
 _PROBE = None
 
 
@@ -292,25 +292,26 @@ def cpu_baseline(w, log, budget_s=12.0):
     threads = allowed
     if os.environ.get("OMP_NUM_THREADS", "").isdigit():
         threads = max(1, min(threads, int(os.environ["OMP_NUM_THREADS"])))
-    pl = I.make_plasma(w, slabs=range(min(8, w.particle_cells()[2 if w.dims == 3 else 1])))
-    E, B = I.laser_fields(w)
+    pl, E, B = workload_inputs(w)
     c = O.Config(w.dims, w.n3, w.dx3, w.dt, w.order, w.bc3)
     X = pl.global_positions(w)
     u = pl.u.T.astype(np.float64)
     q = pl.charges()
 
     def timed(nthreads, budget):
-        # calibrate on a small prefix, then size the sample to the time budget
-        m0 = min(pl.np, 20000)
-        s = O.State(c, X[:m0], u[:m0], q[:m0], E, B)
-        t = time.perf_counter()
-        s.push_deposit(nthreads=nthreads)
-        per = (time.perf_counter() - t) / m0
-        m = int(min(pl.np, max(m0, budget * 0.8 / max(per, 1e-9))))
-        s = O.State(c, X[:m], u[:m], q[:m], E, B)
-        t = time.perf_counter()
-        s.push_deposit(nthreads=nthreads)
-        return m, time.perf_counter() - t, s
+        # grow the sample (a prefix of the workload's particles) until one
+        # pass takes about the time budget; the threaded pass has a fixed
+        # cost (a private current grid per thread, reduced at the end), so
+        # the estimate is refined from each pass
+        m = min(pl.np, 20000)
+        while True:
+            s = O.State(c, X[:m], u[:m], q[:m], E, B)
+            t = time.perf_counter()
+            s.push_deposit(nthreads=nthreads)
+            el = time.perf_counter() - t
+            if m >= pl.np or el >= 0.5 * budget:
+                return m, el, s
+            m = int(min(pl.np, max(2 * m, m * 0.8 * budget / max(el, 1e-9))))
 
     m1, t1, _ = timed(1, 0.35 * budget_s)
     m, t_push, s = timed(threads, 0.65 * budget_s)

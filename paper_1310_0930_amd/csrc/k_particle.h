@@ -296,6 +296,15 @@ __device__ __forceinline__ void gather(const Acc& acc, const R* o, R* Ep, R* Bp)
 }
 
 // ------------------------------------------------------------------ push
+// 1/sqrt(x) and 1/x.  Single precision takes the hardware approximations
+// (v_rsq_f32, v_rcp_f32: about 1 ulp, far below the 1e-5 that the single
+// form is held to) instead of the correctly rounded sequences, which cost
+// about ten instructions each; double precision keeps the exact forms.
+__device__ __forceinline__ float rsqrt_r(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double rsqrt_r(double x) { return 1.0 / sqrt(x); }
+__device__ __forceinline__ float rcp_r(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp_r(double x) { return 1.0 / x; }
+
 // Relativistic Boris step (Sec. 5.2 step iii; Boris is this build's reading
 // of "fully relativistic equations of motion"): half electric kick, magnetic
 // rotation with gamma of the half-kicked momentum, half electric kick.
@@ -304,11 +313,10 @@ __device__ __forceinline__ void boris(R hqm, R* u, const R* E, const R* B) {
   R um[3], t[3], s[3], up[3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) um[c] = u[c] + hqm * E[c];
-  const R gm = sqrt(R(1) + um[0] * um[0] + um[1] * um[1] + um[2] * um[2]);
-  const R hg = hqm / gm;
+  const R hg = hqm * rsqrt_r(R(1) + um[0] * um[0] + um[1] * um[1] + um[2] * um[2]);
 #pragma unroll
   for (int c = 0; c < 3; ++c) t[c] = hg * B[c];
-  const R f = R(2) / (R(1) + t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
+  const R f = R(2) * rcp_r(R(1) + t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
 #pragma unroll
   for (int c = 0; c < 3; ++c) s[c] = f * t[c];
   up[0] = um[0] + (um[1] * t[2] - um[2] * t[1]);
@@ -586,12 +594,12 @@ __device__ __forceinline__ bool push_move(const KParams<R>& P, PState<R>& s, con
                                           const R* Bp, int* sh, R* o1, R& vz, bool& small,
                                           DevFlags* flg) {
   boris<R>(P.hqm, s.u, Ep, Bp);
-  const R gam = sqrt(R(1) + s.u[0] * s.u[0] + s.u[1] * s.u[1] + s.u[2] * s.u[2]);
-  if (!isfinite(gam)) {
+  const R g2 = R(1) + s.u[0] * s.u[0] + s.u[1] * s.u[1] + s.u[2] * s.u[2];
+  if (!isfinite(g2)) {
     raise_flag(flg, PIC_FLAG_NONFINITE);
     return false;
   }
-  const R ig = R(1) / gam;
+  const R ig = rsqrt_r(g2);  // 1/gamma
   small = true;
 #pragma unroll
   for (int d = 0; d < 3; ++d) {

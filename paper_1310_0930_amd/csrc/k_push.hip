@@ -24,23 +24,59 @@
 namespace pic {
 
 // ------------------------------------------------------------------ kernels
-// Per-wavefront queue of virtual segments beyond a particle's first.  About
-// one particle in thirty crosses a stencil-switch plane in a thermal plasma,
-// but that puts a crossing in almost every 64-lane wavefront: depositing the
-// extra segments in place would run the deposit twice per wavefront.
-// Instead every lane deposits its first segment, extra segments are queued
-// (structure of arrays in LDS) and deposited 64 at a time.  Used where the
-// queue still fits next to the tile's field and current regions.
+// Per-wavefront queue of the particles whose path crosses a stencil-switch
+// plane.  A path that stays in one piece of the shape along every axis is a
+// single virtual segment whose ends are the particle's old and new offsets
+// in that piece's frame (nearly every particle of a thermal plasma); a
+// crossing path is split into up to DIMS+1 segments (Sec. 5.2 step iv).
+// About one particle in thirty crosses in a warm plasma, which puts a
+// crossing in almost every 64-lane wavefront: splitting in place would run
+// the split logic and the extra segments' deposit for the whole wavefront
+// each time.  Instead the main loop deposits only single-segment paths, and
+// crossing paths are queued (structure of arrays in LDS) and deposited 64 at
+// a time, each lane splitting its own path.  Used where the queue still fits
+// next to the tile's field and current regions.
 template <int DIMS, int ORDER, typename R>
-struct SegQueue {
+struct CrossQueue {
   using G = Geo<DIMS, ORDER, R>;
-  static constexpr int CAP = 80;  // records per wavefront
+  static constexpr int CAP = 96;  // records per wavefront
   static constexpr int NW = G::NT / 64;
-  static constexpr int NV = 8;  // q, fz, xa[3], xb[3]
+  static constexpr int NV = 2 * DIMS + 2;  // o0[D], o1[D], q, q v_z
   static constexpr size_t bytes = (size_t)NW * CAP * (sizeof(int) + NV * sizeof(R));
-  static constexpr bool on = G::lds_bytes + bytes <= 160 * 1024;
+  static constexpr bool on = G::lds_bytes + bytes + 64 <= 160 * 1024;
   static constexpr int LEN = on ? NW * CAP : 1;
 };
+
+// A queued path: its old cell in the current region and its cell shifts,
+// packed into one word (2 bits per axis above 24 bits of cell).
+__device__ __forceinline__ int pack_path(int pbase, const int* sh) {
+  return pbase | ((sh[0] + 1) << 24) | ((sh[1] + 1) << 26) | ((sh[2] + 1) << 28);
+}
+__device__ __forceinline__ int unpack_path(int w, int* sh) {
+  sh[0] = ((w >> 24) & 3) - 1;
+  sh[1] = ((w >> 26) & 3) - 1;
+  sh[2] = ((w >> 28) & 3) - 1;
+  return w & 0xffffff;
+}
+
+// Charge-conserving current of a whole path into the LDS current tile:
+// split at the stencil-switch planes, then each virtual segment on its own
+// stencil.  fz = q v_z (2D: the out-of-plane current per unit time,
+// already on the tile's scale).
+template <int DIMS, int ORDER, typename R>
+__device__ __forceinline__ void deposit_path_lds(double* s_j, int pbase, const R* jf, const R* o0,
+                                                 const int* sh, const R* o1, R q, R fz) {
+  Split<DIMS, R> S;
+  split_path<DIMS, ORDER, R>(S, o0, sh, o1);
+  LdsCurrent<DIMS, ORDER, R> sink{s_j, pbase, s_j};
+  for (int sg = 0; sg <= S.m; ++sg) {
+    R xa[3], xb[3], ft;
+    int base[3];
+    segment_ends<DIMS, ORDER, R>(S, sg, xa, xb, base, ft);
+    sink.segment(base);
+    deposit_segment<DIMS, ORDER, R>(sink, jf, xa, xb, q, fz * ft);
+  }
+}
 
 // Tiles for persistent workgroups.  Tiles are split into 8 contiguous
 // ranges, one per XCD: a workgroup takes tiles from its own XCD's range
@@ -76,6 +112,9 @@ __device__ __forceinline__ long long sext48(long long x) {
   return (long long)((unsigned long long)x << 16) >> 16;
 }
 
+// First particle of batch b for this lane.
+__device__ __forceinline__ int pbase_of_batch(int pbeg, int b, int lane) { return pbeg + 64 * b + lane; }
+
 // Next batch of 64 particles of the current tile for this wavefront.
 __device__ __forceinline__ int take_batch(int* ctr) {
   int b = 0;
@@ -96,10 +135,10 @@ __global__ void __launch_bounds__((Geo<DIMS, ORDER, R>::NT)) k_push_tile(
     KParams<R> P, DParts<R> pa, DFields<R> F, const int* __restrict__ starts,
     int* __restrict__ deferred, DevFlags* flg) {
   using G = Geo<DIMS, ORDER, R>;
-  using Q = SegQueue<DIMS, ORDER, R>;
+  using Q = CrossQueue<DIMS, ORDER, R>;
   __shared__ R s_eb[6 * G::e_vol];
   __shared__ double s_j[3 * G::j_vol];
-  __shared__ int q_idx[Q::LEN];
+  __shared__ int q_path[Q::LEN];
   __shared__ R q_val[Q::NV][Q::LEN];
   // Tile ids two deep: while tile i runs, slot (i+1)&1 holds tile i+1
   // (tile id, first and end particle) and thread 0 resolves tile i+2 into
@@ -201,8 +240,27 @@ __global__ void __launch_bounds__((Geo<DIMS, ORDER, R>::NT)) k_push_tile(
     }
     const int lane = threadIdx.x & 63;
     const int qb = (threadIdx.x >> 6) * Q::CAP;  // this wavefront's queue
-    int qn = 0;                                  // queued records (wavefront-uniform)
-    LdsCurrent<DIMS, ORDER, R> qsink{s_j, 0, s_j};
+    int qn = 0;                                  // queued paths (wavefront-uniform)
+    // One whole-wavefront round over the last `cnt` queued paths: every lane
+    // splits its path and deposits all of its segments.
+    auto cross_round = [&](int cnt) {
+      __builtin_amdgcn_wave_barrier();
+      if (lane < cnt) {
+        const int r = qb + qn - cnt + lane;
+        int shq[3];
+        const int pb = unpack_path(q_path[r], shq);
+        R a0[3] = {R(0), R(0), R(0)}, a1[3] = {R(0), R(0), R(0)};
+#pragma unroll
+        for (int d = 0; d < DIMS; ++d) {
+          a0[d] = q_val[d][r];
+          a1[d] = q_val[DIMS + d][r];
+        }
+        deposit_path_lds<DIMS, ORDER, R>(s_j, pb, jf, a0, shq, a1, q_val[2 * DIMS][r],
+                                         q_val[2 * DIMS + 1][r]);
+      }
+      __builtin_amdgcn_wave_barrier();
+      qn -= cnt;
+    };
 
     // Wavefronts take batches of 64 consecutive particles from a counter in
     // LDS, so that the wavefronts the SIMD arbiter serves first take more
@@ -210,12 +268,12 @@ __global__ void __launch_bounds__((Geo<DIMS, ORDER, R>::NT)) k_push_tile(
     // past the end are idle) so that whole-wavefront queue rounds see every
     // lane.  The next batch is taken, and its particle state loaded, one
     // iteration ahead.
-    int p = pbeg + 64 * take_batch(&s_batch) + lane, pn;
+    int p = pbase_of_batch(pbeg, take_batch(&s_batch), lane), pn;
     PState<R> nxt;
     if (p < pend) nxt = load_particle<DIMS, R>(pa, p, P.q_const);
     for (; p - lane < pend; p = pn) {
       PState<R> s = nxt;
-      pn = pbeg + 64 * take_batch(&s_batch) + lane;
+      pn = pbase_of_batch(pbeg, take_batch(&s_batch), lane);
       if (pn < pend) nxt = load_particle<DIMS, R>(pa, pn, P.q_const);
       bool valid = p < pend && s.cl >= 0;
       int c3[3] = {0, 0, 0};
@@ -256,72 +314,52 @@ __global__ void __launch_bounds__((Geo<DIMS, ORDER, R>::NT)) k_push_tile(
           valid = false;
         }
       }
-      Split<DIMS, R> S;
-      S.m = 0;
       const int pbase = ((l[2] - G::j_lo_z) * G::jx + (l[1] - G::j_lo)) * G::jx + (l[0] - G::j_lo);
-      if (valid) {
-        split_path<DIMS, ORDER, R>(S, s.o, sh, o1);
-        R xa[3], xb[3], ft;
-        int base[3];
-        segment_ends<DIMS, ORDER, R>(S, 0, xa, xb, base, ft);
+      // A path that stays in the same piece of the shape along every axis is
+      // one virtual segment from the old to the new offset in that piece's
+      // frame, on the stencil of the old cell's piece.
+      R xa[3] = {R(0), R(0), R(0)}, xb[3] = {R(0), R(0), R(0)};
+      int base[3] = {0, 0, 0};
+      bool single = valid;
+#pragma unroll
+      for (int d = 0; d < DIMS; ++d) {
+        const int k0 = piece_node<ORDER>(s.o[d], xa[d]);
+        const int k1 = sh[d] + piece_node<ORDER>(o1[d], xb[d]);
+        single = single && k0 == k1;
+        base[d] = k0 - ORDER / 2;
+      }
+      const bool cross = valid && !single;
+      const R fz = s.q * vz * zs;
+      if (single) {
         LdsCurrent<DIMS, ORDER, R> sink{s_j, pbase, s_j};
         sink.segment(base);
-        deposit_segment<DIMS, ORDER, R>(sink, jf, xa, xb, s.q, s.q * vz * ft * zs);
-        store_particle<DIMS, R>(pa, p, s, o1, new_cell<DIMS, R>(P, c3, sh));
+        deposit_segment<DIMS, ORDER, R>(sink, jf, xa, xb, s.q, fz);
       }
-      // segments after the first
-      const int nx = valid ? S.m : 0;
-      const unsigned long long b0 = __ballot(nx & 1), b1 = __ballot(nx & 2);
-      const int total = (int)(__popcll(b0) + 2 * __popcll(b1));
-      if (total == 0) continue;
-      if (Q::on && qn + total <= Q::CAP) {
-        const unsigned long long below = (1ull << lane) - 1ull;
-        int pos = qn + (int)(__popcll(b0 & below) + 2 * __popcll(b1 & below));
-        for (int sg = 1; sg <= nx; ++sg, ++pos) {
-          R xa[3], xb[3], ft;
-          int base[3];
-          segment_ends<DIMS, ORDER, R>(S, sg, xa, xb, base, ft);
-          q_idx[qb + pos] = pbase + (base[2] * G::jx + base[1]) * G::jx + base[0];
-          q_val[0][qb + pos] = s.q;
-          q_val[1][qb + pos] = s.q * vz * ft * zs;
+      if (valid) store_particle<DIMS, R>(pa, p, s, o1, new_cell<DIMS, R>(P, c3, sh));
+      // paths that cross a stencil-switch plane
+      const unsigned long long cm = __ballot(cross);
+      if (cm == 0ull) continue;
+      if constexpr (Q::on) {
+        const int nc = (int)__popcll(cm);
+        if (qn + nc > Q::CAP) cross_round(qn < 64 ? qn : 64);
+        const int pos = qb + qn + (int)__popcll(cm & ((1ull << lane) - 1ull));
+        if (cross) {
+          q_path[pos] = pack_path(pbase, sh);
 #pragma unroll
-          for (int d = 0; d < 3; ++d) {
-            q_val[2 + d][qb + pos] = xa[d];
-            q_val[5 + d][qb + pos] = xb[d];
+          for (int d = 0; d < DIMS; ++d) {
+            q_val[d][pos] = s.o[d];
+            q_val[DIMS + d][pos] = o1[d];
           }
+          q_val[2 * DIMS][pos] = s.q;
+          q_val[2 * DIMS + 1][pos] = fz;
         }
-        qn += total;
-        while (qn >= 64) {  // one whole-wavefront round from the queue's end
-          __builtin_amdgcn_wave_barrier();
-          const int r = qb + qn - 64 + lane;
-          const R xa[3] = {q_val[2][r], q_val[3][r], q_val[4][r]};
-          const R xb[3] = {q_val[5][r], q_val[6][r], q_val[7][r]};
-          qsink.seg = s_j + q_idx[r];
-          deposit_segment<DIMS, ORDER, R>(qsink, jf, xa, xb, q_val[0][r], q_val[1][r]);
-          __builtin_amdgcn_wave_barrier();
-          qn -= 64;
-        }
-      } else {  // queue full (or not available): deposit in place
-        LdsCurrent<DIMS, ORDER, R> sink{s_j, pbase, s_j};
-        for (int sg = 1; sg <= nx; ++sg) {
-          R xa[3], xb[3], ft;
-          int base[3];
-          segment_ends<DIMS, ORDER, R>(S, sg, xa, xb, base, ft);
-          sink.segment(base);
-          deposit_segment<DIMS, ORDER, R>(sink, jf, xa, xb, s.q, s.q * vz * ft * zs);
-        }
+        qn += nc;
+        if (qn >= 64) cross_round(64);
+      } else {  // no room for a queue: split in place
+        if (cross) deposit_path_lds<DIMS, ORDER, R>(s_j, pbase, jf, s.o, sh, o1, s.q, fz);
       }
     }
-    if (Q::on && qn > 0) {  // drain the queue
-      __builtin_amdgcn_wave_barrier();
-      if (lane < qn) {
-        const int r = qb + lane;
-        const R xa[3] = {q_val[2][r], q_val[3][r], q_val[4][r]};
-        const R xb[3] = {q_val[5][r], q_val[6][r], q_val[7][r]};
-        qsink.seg = s_j + q_idx[r];
-        deposit_segment<DIMS, ORDER, R>(qsink, jf, xa, xb, q_val[0][r], q_val[1][r]);
-      }
-    }
+    if (Q::on && qn > 0) cross_round(qn);  // drain the queue
     // (the opaque copy keeps the compiler from forming the next tile's
     // addresses before the particle loop, where registers are scarce)
     int nt = next;

@@ -35,10 +35,9 @@ struct SortParams {
   int ntiles;
   int dims;
   FastDiv dn0, dn1;
-  // the push kernel's LDS field region: row and plane strides (elements) and
-  // the number of distinct bank positions of an element (32 four-byte
-  // banks: 32 for single, 16 for double precision)
-  int rs1, rs2, rmod;
+  // row and plane strides (elements) of the push kernel's LDS current
+  // region, whose element indices decide the lanes' banks
+  int rs1, rs2;
 };
 
 __device__ __forceinline__ int tile_key(const SortParams& S, int cl, int ncell) {
@@ -282,75 +281,87 @@ struct PVal {
   }
 };
 
-// In-bin order of a tile's cells.  A bin's cells hold one particle each
-// with one stencil shape, so in the push every LDS access of a wavefront is
-// the lanes' cell base addresses plus one common offset; lanes whose bases
-// fall on the same bank serialize.  Cells are ranked by (k, r) where r is
-// the bank position of the cell's base in the field region and k counts
-// the earlier cells with the same r: consecutive cells of the order cycle
-// through the bank positions, and so do consecutive lanes of a bin that
-// holds most of the tile's cells.  One workgroup; order[lc] = rank of cell
-// lc.
+// Bank residues of a tile's cells.  In the push every LDS access of a
+// wavefront is the lanes' cell base addresses plus one offset common to
+// the lanes of one class (one stencil shape).  The LDS serves a wavefront
+// 16 lanes at a time from 32 four-byte banks, and the current tile's
+// 8-byte atomics (and the double-precision field reads) take two banks
+// each: 16 lanes go through without conflict when their cells' element
+// indices in the current region differ modulo 16 (the residue; the
+// single-precision field reads, one bank each, then differ modulo 32 as
+// well where the two regions share their strides).  One workgroup lists the
+// tile's cells by residue: order[0 .. ncells) = cells sorted by (residue,
+// cell), order[TILE_CELLS_MAX + r] = first entry of residue r (r <= RES).
+constexpr int RES = 16;
 constexpr int ORDER_NT = 512;
+constexpr int TILE_CELLS_MAX = 512;
+__device__ __forceinline__ int cell_residue(const SortParams& S, int lc) {
+  const int lx = lc % S.T[0], ly = (lc / S.T[0]) % S.T[1], lz = lc / (S.T[0] * S.T[1]);
+  return (lx + S.rs1 * ly + S.rs2 * lz) % RES;
+}
+
 __global__ void __launch_bounds__(ORDER_NT) k_sort_order(SortParams S, int* __restrict__ order) {
-  __shared__ int cnt[32];
+  __shared__ int cnt[RES];
   __shared__ int res[ORDER_NT];
   const int ncells = S.T[0] * S.T[1] * S.T[2];
   const int lc = threadIdx.x;
-  if (lc < 32) cnt[lc] = 0;
-  int r = 0, k = 0;
+  if (lc < RES) cnt[lc] = 0;
+  int r = 0;
   if (lc < ncells) {
-    const int lx = lc % S.T[0], ly = (lc / S.T[0]) % S.T[1], lz = lc / (S.T[0] * S.T[1]);
-    r = (lx + S.rs1 * ly + S.rs2 * lz) % S.rmod;
+    r = cell_residue(S, lc);
     res[lc] = r;
   }
   __syncthreads();
-  if (lc < ncells) {
-    atomicAdd(&cnt[r], 1);
-    for (int c = 0; c < lc; ++c) k += res[c] == r;
-  }
+  if (lc < ncells) atomicAdd(&cnt[r], 1);
   __syncthreads();
   if (lc < ncells) {
     int pos = 0;
-    for (int q = 0; q < S.rmod; ++q) pos += min(cnt[q], k) + (q < r && cnt[q] > k ? 1 : 0);
-    order[lc] = pos;
+    for (int q = 0; q < r; ++q) pos += cnt[q];
+    for (int c = 0; c < lc; ++c) pos += res[c] == r;
+    order[pos] = lc;
+  }
+  if (lc <= RES) {
+    int st = 0;
+    for (int q = 0; q < lc; ++q) st += cnt[q];
+    order[TILE_CELLS_MAX + lc] = st;
   }
 }
 
 // Placement of one tile's particles (one workgroup per tile) from the
 // scatter's copy back into the particle arrays.  Pass 1 gives every particle
-// its class and its rank within (cell, class) from LDS counters, and counts
-// the tile's NB bins (class, min(rank, last bucket)); pass 2 puts each
-// particle at its bin's start plus its place in the bin: in a bin below the
-// class's last rank bucket every cell appears once, so the k-th cell of the
-// bin (in cell order, from a bit mask of the bin's cells) takes slot k; the
-// last bucket is filled in arrival order.
+// its class and its rank within (cell, class) from LDS counters; the tile's
+// NB bins are (class, min(rank, last bucket)).  In a bin below the class's
+// last rank bucket every cell appears once; its cells are ranked by (k, r)
+// with r the cell's residue and k the number of the bin's cells of the same
+// residue before it (in cell order): the bin cycles through the residues it
+// holds, so every 16 consecutive lanes of a full cycle fall on distinct
+// banks.  One thread per (class, residue) walks that residue's cells to find
+// k for every rank level; pass 2 puts each particle at its bin's start plus
+// its rank in the bin.  The last bucket is filled in arrival order.
 constexpr int PLACE_NT = 512;
 constexpr int PLACE_SRC_MAX = 8192;
-constexpr int TILE_CELLS_MAX = 512;
 template <typename R>
 __global__ void __launch_bounds__(PLACE_NT) k_sort_place(SortArrays<R> A, SortParams S,
                                                           const int* __restrict__ tstart,
                                                           const int* __restrict__ order,
                                                           int* __restrict__ scratch, int dims) {
-  constexpr int W = TILE_CELLS_MAX / 32;  // mask words per bin
-  __shared__ int cnt[TILE_CELLS_MAX * 8];
-  __shared__ unsigned mask[NB][W];
-  __shared__ int pre[NB][W];
+  __shared__ int cnt[TILE_CELLS_MAX * 8];        // particles per (class, cell)
+  __shared__ unsigned char kk[NB][TILE_CELLS_MAX];  // k of a cell in a bin
+  __shared__ int cntb[NB][RES];                  // cells per (bin, residue)
   __shared__ int binc[NB];
   __shared__ int bin0[NB];
-  __shared__ int ord[TILE_CELLS_MAX];
-  __shared__ int inv[TILE_CELLS_MAX];
+  __shared__ int ord[TILE_CELLS_MAX + RES + 1];
+  __shared__ unsigned char res[TILE_CELLS_MAX];
   __shared__ int src[PLACE_SRC_MAX];  // source of each slot of the tile
   const int t = blockIdx.x;
   const int beg = tstart[t], end = tstart[t + 1];
   if (beg == end) return;
   const int ncells = S.T[0] * S.T[1] * S.T[2];
   for (int i = threadIdx.x; i < ncells; i += PLACE_NT) {
-    const int o = order[i];
-    ord[i] = o;
-    inv[o] = i;
+    ord[i] = order[i];
+    res[i] = (unsigned char)cell_residue(S, i);
   }
+  for (int i = threadIdx.x; i <= RES; i += PLACE_NT) ord[TILE_CELLS_MAX + i] = order[TILE_CELLS_MAX + i];
   for (int i = threadIdx.x; i < TILE_CELLS_MAX * 8; i += PLACE_NT) cnt[i] = 0;
   for (int i = threadIdx.x; i < NB; i += PLACE_NT) binc[i] = 0;
   __syncthreads();
@@ -392,44 +403,38 @@ __global__ void __launch_bounds__(PLACE_NT) k_sort_place(SortArrays<R> A, SortPa
         int cls = (po[k][0] >= R(0.5) ? 1 : 0) | (po[k][1] >= R(0.5) ? 2 : 0);
         if (dims == 3) cls |= po[k][2] >= R(0.5) ? 4 : 0;
         const int rank = atomicAdd(&cnt[cls * TILE_CELLS_MAX + cell], 1);
-        // from here on a cell is named by its rank in the in-bin order
-        scratch[i] = (cls * rb + min(rank, rb - 1)) * TILE_CELLS_MAX + ord[cell];
+        scratch[i] = (cls * rb + min(rank, rb - 1)) * TILE_CELLS_MAX + cell;
       }
     }
   }
   __syncthreads();
-  // bin masks from the counts: bin (class, r < last) holds cell c iff c has
-  // more than r particles of that class; one thread per (class, mask word),
-  // which also counts the class's last bucket
-  if (threadIdx.x < (1 << dims) * W) {
-    const int cls = threadIdx.x / W, w = threadIdx.x % W;
-    constexpr int MR = NB / 4 - 1;  // rb - 1 <= MR masks (rb = NB / 2^dims, dims >= 2)
-    unsigned m[MR];
+  // k of every cell in every bin below the last bucket, the bins' residue
+  // counts, and the last buckets' sizes: one thread per (class, residue)
+  if (threadIdx.x < (1 << dims) * RES) {
+    const int cls = threadIdx.x / RES, r = threadIdx.x % RES;
+    constexpr int MR = NB / 4 - 1;  // rb - 1 <= MR rank levels (rb = NB / 2^dims, dims >= 2)
+    int k[MR];
 #pragma unroll
-    for (int r = 0; r < MR; ++r) m[r] = 0u;
+    for (int lv = 0; lv < MR; ++lv) k[lv] = 0;
     int last = 0;
-    for (int bit = 0; bit < 32; ++bit) {
-      const int lcr = w * 32 + bit;
-      if (lcr >= ncells) break;
-      const int n = cnt[cls * TILE_CELLS_MAX + inv[lcr]];
+    for (int i = ord[TILE_CELLS_MAX + r]; i < ord[TILE_CELLS_MAX + r + 1]; ++i) {
+      const int c = ord[i];
+      const int n = cnt[cls * TILE_CELLS_MAX + c];
 #pragma unroll
-      for (int r = 0; r < MR; ++r)
-        if (r < rb - 1 && n > r) m[r] |= 1u << bit;
+      for (int lv = 0; lv < MR; ++lv)
+        if (lv < rb - 1 && n > lv) kk[cls * rb + lv][c] = (unsigned char)k[lv]++;
       last += max(0, n - (rb - 1));
     }
 #pragma unroll
-    for (int r = 0; r < MR; ++r)
-      if (r < rb - 1) mask[cls * rb + r][w] = m[r];
+    for (int lv = 0; lv < MR; ++lv)
+      if (lv < rb - 1) cntb[cls * rb + lv][r] = k[lv];
     if (last) atomicAdd(&binc[cls * rb + rb - 1], last);
   }
   __syncthreads();
-  if (threadIdx.x < NB) {
+  if (threadIdx.x < NB && threadIdx.x % rb < rb - 1) {
     int acc = 0;
-    for (int w = 0; w < W; ++w) {
-      pre[threadIdx.x][w] = acc;
-      acc += __popc(threadIdx.x % rb < rb - 1 ? mask[threadIdx.x][w] : 0u);
-    }
-    if (threadIdx.x % rb < rb - 1) binc[threadIdx.x] = acc;
+    for (int r = 0; r < RES; ++r) acc += cntb[threadIdx.x][r];
+    binc[threadIdx.x] = acc;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -440,20 +445,30 @@ __global__ void __launch_bounds__(PLACE_NT) k_sort_place(SortArrays<R> A, SortPa
     }
   }
   __syncthreads();
+  const int n = end - beg;
+  const bool staged = n <= PLACE_SRC_MAX;
   // Slots.  Stores to scattered slots cost more than loads from them (each
   // partial cache-line write is merged in memory), so when the tile fits,
   // pass 2 records the source of every slot in LDS and pass 3 copies slot by
   // slot (gathered loads, coalesced stores); a larger tile stores directly.
-  const int n = end - beg;
-  const bool staged = n <= PLACE_SRC_MAX;
   for (int i = beg + threadIdx.x; i < end; i += PLACE_NT) {
     const int v = scratch[i];
     const int b = v / TILE_CELLS_MAX, lc = v % TILE_CELLS_MAX;
     int j;
-    if (b % rb < rb - 1)
-      j = bin0[b] + pre[b][lc >> 5] + __popc(mask[b][lc >> 5] & ((1u << (lc & 31)) - 1u));
-    else
-      j = atomicAdd(&bin0[b], 1);  // last bucket (no mask): arrival order
+    if (b % rb < rb - 1) {
+      // rank of (k, r) in the bin: every residue with more than k cells
+      // fills levels 0..k, those below r also level k
+      const int k = kk[b][lc], r = res[lc];
+      int pos = 0;
+#pragma unroll
+      for (int q = 0; q < RES; ++q) {
+        const int c = cntb[b][q];
+        pos += min(c, k) + (q < r && c > k ? 1 : 0);
+      }
+      j = bin0[b] + pos;
+    } else {
+      j = atomicAdd(&bin0[b], 1);  // last bucket: arrival order
+    }
     if (staged) {
       src[j - beg] = i;
     } else {
@@ -485,9 +500,8 @@ __global__ void k_fill_int(int* a, long n, int v) {
 template <int DIMS, int ORDER, typename R>
 static void region_strides_t(SortParams& S) {
   using G = Geo<DIMS, ORDER, R>;
-  S.rs1 = G::ex;
-  S.rs2 = DIMS == 3 ? G::ex * G::ex : 0;
-  S.rmod = sizeof(R) == 4 ? 32 : 16;
+  S.rs1 = G::jx;
+  S.rs2 = DIMS == 3 ? G::jx * G::jx : 0;
 }
 
 template <typename R>
@@ -499,7 +513,6 @@ static void region_strides(int dims, int order, SortParams& S) {
 #undef PIC_RS
   S.rs1 = 1;
   S.rs2 = 1;
-  S.rmod = 32;
 }
 
 template <typename R>

@@ -49,7 +49,7 @@ WsLayout ws_layout(const pic_ctx* ctx, int64_t np) {
   L.keys = off;
   off = align256(off + sizeof(int) * n);
   L.order = off;
-  off = align256(off + sizeof(int) * 512);
+  off = align256(off + sizeof(int) * 1024);
   L.tmp_real = off;
   off = align256(off + R * 7 * n);
   L.total = off;

@@ -151,7 +151,7 @@ struct WsLayout {
   size_t bstart;     // int32[nbins + 1]    bin starts
   size_t bsum;       // int32[nbins / 1024 + 1]  scan block sums
   size_t keys;       // int32[np]           tile of each particle, then its in-tile bin and cell
-  size_t order;      // int32[512]          in-bin order of a tile's cells (bank-balanced)
+  size_t order;      // int32[1024]         a tile's cells listed by bank residue
   size_t tmp_cell;   // int32[np]
   size_t tmp_real;   // R[np * 7]  off[3], u[3], q
   size_t tmp_id;     // int32[np]

@@ -277,19 +277,18 @@ def test_fdtd_eigenmode_3d_oblique_fp64():
 
 # ---------------------------------------------------------------- edge cases
 def _tile_geometry(dims, order, rb):
-    """Tile sizes and the push kernel's LDS field-region strides for a
-    configuration (the tile-kernel geometry), and the number of distinct bank
-    positions of a field sample (32 four-byte banks)."""
+    """Tile sizes and the row/plane strides of the push kernel's LDS current
+    region for a configuration (the tile-kernel geometry)."""
     wide = order == 4 or (rb == 8 and order == 3)
     if dims == 2:
         T, TZ, A = 16, 1, 2
     else:
         T = 4 if (order == 4 and rb == 8) else 8
         TZ, A = (4 if wide else T), 1
-    g_lo = -2 if order >= 3 else -1
-    g_hi = 1 if order == 1 else (3 if order == 4 else 2)
-    ex = T + 2 * A + g_hi - g_lo
-    return T, TZ, ex, (ex * ex if dims == 3 else 0), (32 if rb == 4 else 16)
+    d_lo = -2 if order >= 3 else -1
+    d_hi = 3 if order >= 3 else 2
+    jx = T + 2 * A + d_hi - d_lo
+    return T, TZ, jx, (jx * jx if dims == 3 else 0)
 
 
 def _check_sorted(w, rb, pl, st):
@@ -302,7 +301,7 @@ def _check_sorted(w, rb, pl, st):
     np.testing.assert_array_equal(st["u"], pl.u[:, ids].astype(np.float64))
     D = w.dims
     n0, n1, _ = w.n3
-    T, TZ, ex, plane, rmod = _tile_geometry(D, w.order, rb)
+    T, TZ, jx, plane = _tile_geometry(D, w.order, rb)
     c = st["cell"]
     cx, cy, cz = c % n0, (c // n0) % n1, c // (n0 * n1)
     nt0, nt1 = -(-n0 // T), -(-n1 // T)
@@ -316,21 +315,17 @@ def _check_sorted(w, rb, pl, st):
     o = st["off"]
     cls = sum((o[d] >= 0.5).astype(np.int64) << d for d in range(D))
     rbk = 32 >> D
-    # in-bin cell order: the tile's cells ranked by (k, residue), the residue
-    # being the cell's base address in the push kernel's LDS field region
-    # modulo the bank positions and k counting the earlier cells with the
-    # same residue
-    nc = T * T * TZ
-    lc_all = np.arange(nc)
-    res = (lc_all % T + ex * ((lc_all // T) % T) + plane * (lc_all // (T * T))) % rmod
-    occ = np.array([np.sum(res[:i] == res[i]) for i in range(nc)])
-    order = np.empty(nc, dtype=np.int64)
-    order[np.lexsort((res, occ))] = np.arange(nc)
-    lcell = (cx % T) + T * ((cy % T) + T * (cz % TZ))
+    # inside a bin below the last bucket the cells are ranked by (k, r): r
+    # is the residue modulo 16 of the cell's element index in the current
+    # region, k the number of the bin's cells with the same residue that
+    # come before it in cell order
+    lx, ly, lz = cx % T, cy % T, cz % TZ
+    lcell = lx + T * (ly + T * lz)
+    resid = (lx + jx * ly + plane * lz) % 16
     nlast = 0
     for t in np.unique(key):
         m = key == t
-        cells, kt, lt = c[m], cls[m], lcell[m]
+        cells, kt, lt, rt = c[m], cls[m], lcell[m], resid[m]
         assert np.all(np.diff(kt) >= 0), t
         seen = {}
         rank = np.empty(cells.size, dtype=np.int64)
@@ -339,10 +334,20 @@ def _check_sorted(w, rb, pl, st):
             seen[(cl, k)] = rank[i] + 1
         for k in np.unique(kt):
             assert np.all(np.diff(np.minimum(rank[kt == k], rbk - 1)) >= 0), (t, k)
-            # a bin below the last rank bucket holds each cell once, ordered
-            # by the bank-balanced cell rank
             for r in range(rbk - 1):
-                assert np.all(np.diff(order[lt[(kt == k) & (rank == r)]]) > 0), (t, k, r)
+                sel = np.flatnonzero((kt == k) & (rank == r))
+                got = lt[sel]
+                assert len(np.unique(got)) == len(got), (t, k, r)  # each cell once
+                if len(got) == 0:
+                    continue
+                byc = np.argsort(got, kind="stable")
+                lev = np.empty(len(got), dtype=np.int64)
+                cnt = {}
+                for i in byc:  # in cell order
+                    lev[i] = cnt.get(rt[sel][i], 0)
+                    cnt[rt[sel][i]] = lev[i] + 1
+                want = got[np.lexsort((rt[sel], lev))]
+                assert np.array_equal(got, want), (t, k, r)
         nlast += int(np.sum(rank >= rbk - 1))
     return nlast
 
