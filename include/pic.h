@@ -57,7 +57,8 @@ enum pic_status {
   PIC_EHIP = -3,     /* a HIP runtime call failed (no device, launch error) */
   PIC_ESTATE = -4,   /* call order violated (e.g. push before any sort) */
   PIC_EDEVICE = -5,  /* sticky device flags were raised (see pic_read_flags) */
-  PIC_ELDS = -6      /* tile geometry does not fit the 160 KB LDS of a CU */
+  PIC_ELDS = -6,     /* tile geometry does not fit the 160 KB LDS of a CU */
+  PIC_ESCRATCH = -7  /* the static scratch of pic_field_advance_static is too small */
 };
 
 enum pic_bc { PIC_BC_PERIODIC = 0, PIC_BC_OPEN = 1 };
@@ -181,6 +182,20 @@ int pic_push_deposit(pic_ctx* ctx, pic_particles* p, const pic_fields* f, void* 
  * with Mur first-order absorbing updates of the tangential E on open faces;
  * B -= dt/2 C E (Sec. 2: FDTD method, local solver, Sec. 3). */
 int pic_field_advance(pic_ctx* ctx, pic_fields* f, void* ws, void* stream);
+
+/* pic_field_advance without a workspace, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation): same arguments and result as
+ * pic_field_advance.  Its scratch -- the E samples next to open faces,
+ * saved between the Yee and the Mur updates, 4 n_a n_b reals per open axis
+ * (n_a, n_b the grid sizes across that axis) -- lives in a static device
+ * array of 16 MiB per GPU (each GPU the library runs on holds it until the
+ * process ends); a grid that needs more returns PIC_ESCRATCH before any
+ * launch.  Nothing in it has to start at zero: every call writes the saved
+ * planes before reading them.  All calls on one GPU share that array, so
+ * calls that overlap on one GPU (two streams, two host threads) race.  It
+ * allocates nothing: no hipMalloc, hipFree or allocating library call. */
+int pic_field_advance_static(pic_ctx* ctx, pic_fields* f, void* stream);
 
 /* `nsteps` full steps: pic_sort when due (every sort_every steps, counted
  * per context, and before the first push; p->np drops to the live count at

@@ -15,6 +15,8 @@
 // inward.  Samples on two open faces (edges) are done in a second pass along
 // the lower such axis.  Samples beyond the last node (half-integer positions)
 // are outside the domain, are never written and are read as zero.
+#include <mutex>
+
 #include "k_common.h"
 
 namespace pic {
@@ -271,8 +273,11 @@ __global__ void k_fill3_zero(R* a, R* b, R* c, long n) {
   }
 }
 
+// `save` holds the E samples next to open faces between the Yee update and
+// the Mur updates (mur_len(cfg) reals); every call writes them before it
+// reads them.
 template <typename R>
-static int launch_fa(const pic_ctx* ctx, const pic_fields* f, void* ws, hipStream_t s) {
+static int launch_fa(const pic_ctx* ctx, const pic_fields* f, R* save, hipStream_t s) {
   const pic_config& cf = ctx->cfg;
   FdParams P;
   P.dims = cf.dims;
@@ -297,8 +302,6 @@ static int launch_fa(const pic_ctx* ctx, const pic_fields* f, void* ws, hipStrea
     B[c] = (R*)f->B[c];
     J[c] = (R*)f->J[c];
   }
-  WsLayout L = ws_layout(ctx, 0);
-  R* save = (R*)((char*)ws + L.mur);
   MurPlanes M;
   long off = 0;
   for (int d = 0; d < 3; ++d) {
@@ -344,8 +347,41 @@ static int launch_fa(const pic_ctx* ctx, const pic_fields* f, void* ws, hipStrea
 }
 
 int launch_field_advance(const pic_ctx* ctx, const pic_fields* f, void* ws, hipStream_t s) {
-  return ctx->cfg.real_bytes == 8 ? launch_fa<double>(ctx, f, ws, s)
-                                  : launch_fa<float>(ctx, f, ws, s);
+  char* save = (char*)ws + ws_layout(ctx, 0).mur;
+  return ctx->cfg.real_bytes == 8 ? launch_fa<double>(ctx, f, (double*)save, s)
+                                  : launch_fa<float>(ctx, f, (float*)save, s);
+}
+
+// Scratch of pic_field_advance_static: the saved E planes next to open
+// faces, in a file-scope device array instead of the caller's workspace
+// (one copy per GPU the library runs on, held until the process ends).  In
+// host code `scratch` is only a host-side stand-in for the symbol; its
+// device address on each GPU comes from hipGetSymbolAddress, taken once per
+// device with that device current and kept in static_scratch_ptr.
+static __device__ __align__(256) unsigned char scratch[STATIC_SCRATCH_BYTES];
+static void* static_scratch_ptr[MAX_DEVICES];
+static std::mutex static_scratch_mu;
+
+int static_scratch_init(int device) {
+  if (device < 0 || device >= MAX_DEVICES) return (int)hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(static_scratch_mu);
+  if (static_scratch_ptr[device]) return 0;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) return e != hipSuccess ? (int)e : (int)hipErrorInvalidSymbol;
+  static_scratch_ptr[device] = ptr;
+  return 0;
+}
+
+int launch_field_advance_static(const pic_ctx* ctx, const pic_fields* f, hipStream_t s) {
+  void* save = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(static_scratch_mu);
+    if (ctx->device >= 0 && ctx->device < MAX_DEVICES) save = static_scratch_ptr[ctx->device];
+  }
+  if (!save) return (int)hipErrorNotInitialized;
+  return ctx->cfg.real_bytes == 8 ? launch_fa<double>(ctx, f, (double*)save, s)
+                                  : launch_fa<float>(ctx, f, (float*)save, s);
 }
 
 // ------------------------------------------------------------------ adjoint

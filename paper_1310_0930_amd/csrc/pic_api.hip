@@ -156,6 +156,7 @@ int pic_create(const pic_config* cfg, pic_ctx** out) {
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return PIC_EHIP;
+  if (static_scratch_init(dev) != 0) return PIC_EHIP;  // pic_field_advance_static's scratch
   pic_ctx* ctx = new (std::nothrow) pic_ctx();
   if (!ctx) return PIC_EHIP;
   ctx->cfg = *cfg;
@@ -285,6 +286,16 @@ int pic_field_advance(pic_ctx* ctx, pic_fields* f, void* ws, void* stream) {
   if (v) return v;
   if ((v = ensure_device(ctx))) return v;
   return hip_status(launch_field_advance(ctx, f, ws, (hipStream_t)stream));
+}
+
+int pic_field_advance_static(pic_ctx* ctx, pic_fields* f, void* stream) {
+  if (!ctx) return PIC_EINVAL;
+  int v = check_fields(f, true);
+  if (v) return v;
+  if ((size_t)mur_len(ctx->cfg) * (size_t)ctx->cfg.real_bytes > STATIC_SCRATCH_BYTES)
+    return PIC_ESCRATCH;
+  if ((v = ensure_device(ctx))) return v;
+  return hip_status(launch_field_advance_static(ctx, f, (hipStream_t)stream));
 }
 
 int pic_step(pic_ctx* ctx, pic_particles* p, pic_fields* f, int32_t nsteps, void* ws, void* stream) {
@@ -533,6 +544,7 @@ const char* pic_strerror(int status) {
     case PIC_ESTATE: return "call order violated (sort the particles first)";
     case PIC_EDEVICE: return "device flags raised";
     case PIC_ELDS: return "tile geometry exceeds the LDS of a compute unit";
+    case PIC_ESCRATCH: return "grid needs more scratch than the static no-allocation buffer holds";
     default: return "unknown status";
   }
 }

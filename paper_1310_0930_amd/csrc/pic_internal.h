@@ -191,6 +191,13 @@ int launch_sort(const pic_ctx* ctx, const pic_particles* p, void* ws, hipStream_
 int launch_push_deposit(const pic_ctx* ctx, const pic_particles* p, const pic_fields* f,
                         void* ws, hipStream_t s, bool accumulate);
 int launch_field_advance(const pic_ctx* ctx, const pic_fields* f, void* ws, hipStream_t s);
+// The no-allocation field advance: its scratch is a static device array of
+// STATIC_SCRATCH_BYTES per GPU, whose address static_scratch_init takes (once
+// per device, with that device current) at context creation.
+constexpr size_t STATIC_SCRATCH_BYTES = (size_t)16 << 20;
+constexpr int MAX_DEVICES = 64;
+int static_scratch_init(int device);
+int launch_field_advance_static(const pic_ctx* ctx, const pic_fields* f, hipStream_t s);
 int launch_field_advance_adjoint(const pic_ctx* ctx, const pic_fields* lam, void* ws, hipStream_t s);
 int launch_push_deposit_adjoint(const pic_ctx* ctx, const pic_particles* p, const pic_fields* f,
                                 const pic_fields* lam_f, pic_particles* lam_p, void* ws,

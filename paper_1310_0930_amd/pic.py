@@ -26,6 +26,7 @@ LIB_PATH = os.path.join(_HERE, "libpic.so")
 _LIB = None
 
 PIC_OK, PIC_EINVAL, PIC_ECOURANT, PIC_EHIP, PIC_ESTATE, PIC_EDEVICE, PIC_ELDS = 0, -1, -2, -3, -4, -5, -6
+PIC_ESCRATCH = -7
 PIC_BC_PERIODIC, PIC_BC_OPEN = 0, 1
 FLAG_NAMES = {1: "nonfinite", 2: "offset", 4: "cell", 8: "overspeed"}
 
@@ -82,6 +83,7 @@ _SIGS = {
     "pic_push_deposit": ([C.c_void_p, C.POINTER(PicParticles), C.POINTER(PicFields), C.c_void_p,
                           C.c_void_p], C.c_int),
     "pic_field_advance": ([C.c_void_p, C.POINTER(PicFields), C.c_void_p, C.c_void_p], C.c_int),
+    "pic_field_advance_static": ([C.c_void_p, C.POINTER(PicFields), C.c_void_p], C.c_int),
     "pic_step": ([C.c_void_p, C.POINTER(PicParticles), C.POINTER(PicFields), C.c_int32, C.c_void_p,
                   C.c_void_p], C.c_int),
     "pic_deposit_rho": ([C.c_void_p, C.POINTER(PicParticles), C.c_void_p, C.c_void_p, C.c_void_p],
@@ -185,6 +187,11 @@ def pic_push_deposit(ctx, parts: PicParticles, fields: PicFields, ws, stream=Non
 def pic_field_advance(ctx, fields: PicFields, ws, stream=None):
     _check(lib().pic_field_advance(ctx, C.byref(fields), C.c_void_p(ws), _stream(stream)),
            "pic_field_advance")
+
+
+def pic_field_advance_static(ctx, fields: PicFields, stream=None):
+    _check(lib().pic_field_advance_static(ctx, C.byref(fields), _stream(stream)),
+           "pic_field_advance_static")
 
 
 def pic_step(ctx, parts: PicParticles, fields: PicFields, nsteps, ws, stream=None):

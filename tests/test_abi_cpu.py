@@ -32,7 +32,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_strerror_names_every_status():
-    for st in (0, -1, -2, -3, -4, -5, -6):
+    for st in (0, -1, -2, -3, -4, -5, -6, -7):
         assert P.strerror(st) and "unknown" not in P.strerror(st)
     assert "unknown" in P.strerror(12345)
 
