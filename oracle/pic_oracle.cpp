@@ -471,6 +471,10 @@ R curl_b_at(const Grid& g, const R* B, int c, long i, long j, long k) {
   return bwd(b, a) - bwd(a, b);
 }
 
+// The field loops below update every sample from values that no other
+// iteration of the same loop writes, so their z planes run in parallel
+// (OpenMP) with results identical to the serial loops.
+
 // Is the storage slot (i,j,k) of a component with staggering st inside the
 // domain?
 inline bool slot_inside(const Grid& g, const int st[3], long i, long j, long k) {
@@ -484,6 +488,9 @@ void half_b(const Grid& g, const R* E, R* B, double h) {
   std::vector<R> cE(3 * nc);
   for (int c = 0; c < 3; ++c) {
     int sb[3] = {stag_b(c, 0), stag_b(c, 1), stag_b(c, 2)};
+#ifdef _OPENMP
+    #pragma omp parallel for schedule(static)
+#endif
     for (long k = 0; k < g.n[2]; ++k)
       for (long j = 0; j < g.n[1]; ++j)
         for (long i = 0; i < g.n[0]; ++i)
@@ -492,6 +499,9 @@ void half_b(const Grid& g, const R* E, R* B, double h) {
   }
   for (int c = 0; c < 3; ++c) {
     int sb[3] = {stag_b(c, 0), stag_b(c, 1), stag_b(c, 2)};
+#ifdef _OPENMP
+    #pragma omp parallel for schedule(static)
+#endif
     for (long k = 0; k < g.n[2]; ++k)
       for (long j = 0; j < g.n[1]; ++j)
         for (long i = 0; i < g.n[0]; ++i)
@@ -518,6 +528,9 @@ void advance_e(const Grid& g, R* E, const R* B, const R* J) {
   // Yee update of every interior sample
   for (int c = 0; c < 3; ++c) {
     int se[3] = {stag_e(c, 0), stag_e(c, 1), stag_e(c, 2)};
+#ifdef _OPENMP
+    #pragma omp parallel for schedule(static)
+#endif
     for (long k = 0; k < g.n[2]; ++k)
       for (long j = 0; j < g.n[1]; ++j)
         for (long i = 0; i < g.n[0]; ++i) {
@@ -536,6 +549,9 @@ void advance_e(const Grid& g, R* E, const R* B, const R* J) {
   for (int pass = 1; pass <= 2; ++pass)
     for (int c = 0; c < 3; ++c) {
       int se[3] = {stag_e(c, 0), stag_e(c, 1), stag_e(c, 2)};
+#ifdef _OPENMP
+      #pragma omp parallel for schedule(static)
+#endif
       for (long k = 0; k < g.n[2]; ++k)
         for (long j = 0; j < g.n[1]; ++j)
           for (long i = 0; i < g.n[0]; ++i) {

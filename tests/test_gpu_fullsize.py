@@ -156,19 +156,28 @@ _W3D_256_REF = {}
 
 
 def _w3d_256_reference(w, pl, E, B, checkpoints):
-    """Oracle states of the 256x128x128 workload at the given steps (one
-    run, shared by the FP64 and FP32 cases)."""
+    """Oracle states of the 256x128x128 workload at the given steps, and the
+    FP32 conditioning floor there (a second oracle run with one FP32 storage
+    rounding's worth of noise after every step); one run each, shared by the
+    FP64 and FP32 cases."""
     key = (w.name, w.n3, tuple(checkpoints))
     if key not in _W3D_256_REF:
         _W3D_256_REF.clear()
         ref = oracle_state(w, pl, E, B)
-        out, done = {}, 0
+        pert = oracle_state(w, pl, E, B)
+        rng = np.random.default_rng(5)
+        out, floors, done = {}, {}, 0
         for n in checkpoints:
             ref.step(n - done, nthreads=oracle_threads())
+            for _ in range(n - done):
+                pert.step(1, nthreads=oracle_threads())
+                _perturb(pert, 4, rng)
             done = n
             out[n] = ref.copy()
             out[n].alive = ref.alive.copy()
-        _W3D_256_REF[key] = out
+            floors[n] = _floor(ref, pert)
+            say("oracle step", n, "fp32 floor", floors[n])
+        _W3D_256_REF[key] = (out, floors)
     return _W3D_256_REF[key]
 
 
@@ -176,11 +185,14 @@ def _w3d_256_reference(w, pl, E, B, checkpoints):
 def test_w3d_256_cubic_twenty_steps(rb):
     """256x128x128, cubic, ramp + a0 = 4 laser, open y and z (33.5M
     particles), sorted every 4 steps: 20 steps (five re-sorts) on every
-    particle and field sample, checked at each re-sort."""
+    particle and field sample, checked at each re-sort.  FP64 within 1e-12
+    at every check; FP32 within 1e-5 over the first 12 steps and within
+    max(1e-5, 3 x its conditioning floor) after that (the a0 = 4 pulse
+    amplifies storage rounding as in the 512x256 case)."""
     w = I.WORKLOADS["w3d_256_cubic_laser"]
     pl, E, B = inputs_for(w)
     checks = list(range(4, 21, 4))
-    refs = _w3d_256_reference(w, pl, E, B, checks)
+    refs, floors = _w3d_256_reference(w, pl, E, B, checks)
     say("case", w.name, "np", pl.np, "real", rb, "sort every", w.sort_every)
     sim = gpu_sim(w, rb, pl, E, B)
     done = 0
@@ -189,8 +201,16 @@ def test_w3d_256_cubic_twenty_steps(rb):
         done = n
         torch.cuda.synchronize()
         err = compare(w, sim, refs[n])
-        say(w.name, rb, "step", n, err)
-        _check(err, rb, 1e-10 if rb == 8 else 1e-4)
+        say(w.name, rb, "step", n, err, "fp32 floor", floors[n])
+        if rb == 8 or n <= 12:
+            _check(err, rb, 1e-10 if rb == 8 else 1e-4)
+        else:
+            fp, fu, fa = floors[n]
+            assert err["alive_mismatch"] <= max(2, 3 * fa), (n, err, fa)
+            assert err["pos"] <= max(TOL[4], 3 * fp), (n, err, fp)
+            assert err["u"] <= max(TOL[4], 3 * fu), (n, err, fu)
+            for f in ("E", "B", "J"):
+                assert err[f] <= 1e-4, (n, f, err)
 
 
 def test_w3d_256_cubic_narrow_two_hundred_steps():
@@ -309,13 +329,24 @@ def test_w3d_512_whole_step_and_diagnostics():
     e_rho = np.abs(rho1.reshape(rho_o.shape) - rho_o).max() / scale
     gauss_o = O.divergence(cfg, gs.E) - rho_o - g0.reshape(rho_o.shape)
     wf, wk = gs.energies()
-    say("oracle diagnostics: rho err %.2e, gauss max %.3e (gpu %.3e), w_field %.9e (gpu %.9e), "
-        "w_kin %.9e (gpu %.9e)" % (e_rho, np.abs(gauss_o).max(), d1.raw["gauss_max"], wf,
-                                   d1.raw["w_field"], wk, d1.raw["w_kin"]))
+    # the same energies summed pairwise (numpy): the oracle adds its 2e8 and
+    # 2.7e8 terms one after the other, whose rounding reaches N * 2^-53
+    # relative (about 1e-11 here), while pairwise sums stay near 1e-15
+    dV = float(np.prod(w.dx3))
+    wf_p = 0.5 * dV * (np.sum(st["E"] ** 2) + np.sum(st["B"] ** 2))
+    g1 = np.sqrt(1.0 + np.sum(st["u"] ** 2, axis=0))
+    wk_p = dV * np.sum(np.abs(q) * (g1 - 1.0))
+    say("oracle diagnostics: rho err %.2e, gauss max %.3e (gpu %.3e), w_field %.12e / pairwise "
+        "%.12e (gpu %.12e), w_kin %.12e / pairwise %.12e (gpu %.12e)"
+        % (e_rho, np.abs(gauss_o).max(), d1.raw["gauss_max"], wf, wf_p, d1.raw["w_field"], wk,
+           wk_p, d1.raw["w_kin"]))
     assert e_rho <= 1e-12
     assert abs(d1.raw["gauss_max"] - np.abs(gauss_o).max()) <= 1e-12 * scale
-    assert abs(d1.raw["w_field"] - wf) <= 1e-12 * wf
-    assert abs(d1.raw["w_kin"] - wk) <= 1e-12 * max(wk, 1e-300)
+    nf, nk = 6 * st["E"][0].size, pl.np
+    assert abs(d1.raw["w_field"] - wf) <= nf * 2.0 ** -53 * wf
+    assert abs(d1.raw["w_kin"] - wk) <= nk * 2.0 ** -53 * wk
+    assert abs(d1.raw["w_field"] - wf_p) <= 1e-12 * wf_p
+    assert abs(d1.raw["w_kin"] - wk_p) <= 1e-12 * wk_p
     # the physics the diagnostics watch: the FP32 step conserves charge to
     # single precision, and Gauss's law keeps its initial residual up to the
     # rounding of the stored E (each sample within 2^-24 of max |E|, and the
