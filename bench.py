@@ -337,6 +337,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="w3d_128_quadratic", choices=sorted(I.WORKLOADS))
+    ap.add_argument("--sort-every", type=int, default=0, metavar="N",
+                    help="sort every N steps instead of the workload's interval")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quiet", action="store_true")
@@ -364,6 +366,8 @@ def main():
             print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
     w = I.WORKLOADS[a.workload]
+    if a.sort_every > 0:
+        w = w.with_(sort_every=a.sort_every)
     if a.calibrate_copy:
         import torch
         src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")

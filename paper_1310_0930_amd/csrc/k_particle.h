@@ -130,8 +130,15 @@ struct LdsFields {
                                                     int k) const {
     return k < 2 ? r + k * G::ex * G::ex : r2 + (k - 2) * G::ex * G::ex;
   }
+  // One LDS read per value: paired reads (ds_read2) of neighbouring samples
+  // cost gfx950's LDS about twice the cycles of two single reads for the
+  // lane layouts the sort produces (measured with the LDS probe's
+  // push-pattern replay), so the reads go through a volatile pointer, which
+  // keeps their compile-time offsets but stops the compiler from pairing
+  // them.
   __device__ __forceinline__ R at(lds_ptr<const R> rk, int /*comp*/, int i, int j, int /*k*/) const {
-    return rk[j * G::ex + i];
+    using vptr = __attribute__((address_space(3))) const volatile R*;
+    return ((vptr)rk)[j * G::ex + i];
   }
   static __device__ __forceinline__ lds_ptr<const R> pin(lds_ptr<const R> p) {
     uint32_t a = (uint32_t)(uintptr_t)p;

@@ -129,7 +129,8 @@ int lds_probe_run(int op, int stride, int iters, int blocks, void* sink, void* s
 // grid replays pattern v mod npat.  Mode 0: the single-precision gather (six
 // components, 27 reads each at the component's own stencil); 1: the double
 // one; 2: the single form's current deposit (54 ds_add_u64 of one virtual
-// segment); 3: the double form's (ds_add_f64).
+// segment); 3: the double form's (ds_add_f64); 4: the single-precision gather
+// with one ds_read_b32 per value.
 namespace {
 
 constexpr int RX = 13, RV = RX * RX * RX;
@@ -137,9 +138,12 @@ constexpr int RX = 13, RV = RX * RX * RX;
 template <int MODE>
 __global__ void __launch_bounds__(NT) k_lds_pattern(const int* __restrict__ lanes, int npat,
                                                     int iters, uint64_t* sink) {
-  using T = typename std::conditional<MODE == 0, float,
+  // mode 4: the single-precision gather with one 32-bit read per value
+  // (reads through a volatile LDS pointer are not paired into ds_read2)
+  using T = typename std::conditional<MODE == 0 || MODE == 4, float,
             typename std::conditional<MODE == 2, unsigned long long, double>::type>::type;
-  constexpr int COMPS = MODE < 2 ? 6 : 3;
+  constexpr bool GATHER = MODE < 2 || MODE == 4;
+  constexpr int COMPS = GATHER ? 6 : 3;
   __shared__ T lds[COMPS * RV];
   for (int i = threadIdx.x; i < COMPS * RV; i += NT) lds[i] = T(i & 7);
   __syncthreads();
@@ -157,7 +161,7 @@ __global__ void __launch_bounds__(NT) k_lds_pattern(const int* __restrict__ lane
     const bool isb = c >= 3;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      const bool stag = MODE < 2 ? (isb ? d != e : d == e) : false;
+      const bool stag = GATHER ? (isb ? d != e : d == e) : false;
       const int str = d == 0 ? 1 : d == 1 ? RX : RX * RX;
       sh += ((stag ? 0 : cb[d]) - 1) * str;
     }
@@ -169,7 +173,16 @@ __global__ void __launch_bounds__(NT) k_lds_pattern(const int* __restrict__ lane
   for (int it = 0; it < iters; ++it) {
 #pragma unroll
     for (int c = 0; c < COMPS; ++c) {
-      if constexpr (MODE < 2) {
+      if constexpr (MODE == 4) {
+        typedef __attribute__((address_space(3))) const volatile float lf;
+        lf* p = (lf*)(lds + base[c]);
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+          for (int j = 0; j < 3; ++j)
+#pragma unroll
+            for (int i = 0; i < 3; ++i) acc9[3 * k + j] += p[i + RX * (j + RX * k)];
+      } else if constexpr (MODE < 2) {
         const T* p = lds + base[c];
 #pragma unroll
         for (int k = 0; k < 3; ++k)
@@ -195,7 +208,7 @@ __global__ void __launch_bounds__(NT) k_lds_pattern(const int* __restrict__ lane
   T acc = T(0);
 #pragma unroll
   for (int r = 0; r < 9; ++r) acc += acc9[r];
-  if constexpr (MODE >= 2) {
+  if constexpr (!GATHER) {
     __syncthreads();
     acc = lds[threadIdx.x];
   }
@@ -220,7 +233,7 @@ extern "C" {
  * -1 for bad arguments. */
 int lds_probe_pattern(int mode, const void* lanes, int npat, int iters, int blocks, void* sink,
                       void* stream, float* ms) {
-  if (mode < 0 || mode > 3 || !lanes || npat < 1 || iters < 1 || blocks < 1 || !sink || !ms)
+  if (mode < 0 || mode > 4 || !lanes || npat < 1 || iters < 1 || blocks < 1 || !sink || !ms)
     return -1;
   hipStream_t s = (hipStream_t)stream;
   hipEvent_t a, b;
@@ -237,7 +250,8 @@ int lds_probe_pattern(int mode, const void* lanes, int npat, int iters, int bloc
       case 0: err = launch_pattern<0>(L, npat, iters, blocks, k, s); break;
       case 1: err = launch_pattern<1>(L, npat, iters, blocks, k, s); break;
       case 2: err = launch_pattern<2>(L, npat, iters, blocks, k, s); break;
-      default: err = launch_pattern<3>(L, npat, iters, blocks, k, s); break;
+      case 3: err = launch_pattern<3>(L, npat, iters, blocks, k, s); break;
+      default: err = launch_pattern<4>(L, npat, iters, blocks, k, s); break;
     }
   }
   if (!err) err = (int)hipEventRecord(b, s);
