@@ -150,12 +150,13 @@ def run_gpu(w, real_bytes, steps, warmup, log):
         if ev is not None:
             ev[1].record()
         sim.field_advance()
+        if ev is not None:
+            ev[2].record()
 
     for k in range(warmup):
         one_step(k)
     torch.cuda.synchronize()
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(steps)]
+    evs = [tuple(torch.cuda.Event(enable_timing=True) for _ in range(3)) for _ in range(steps)]
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -167,18 +168,35 @@ def run_gpu(w, real_bytes, steps, warmup, log):
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
     total_ms = t0.elapsed_time(t1)
-    push_ms = [a.elapsed_time(b) for a, b in evs]
+    push_ms = [a.elapsed_time(b) for a, b, _ in evs]
+    fdtd_ms = [b.elapsed_time(c) for _, b, c in evs]
     flags, nslow = 0, 0
     for s in everyone:
         f_, n_ = s.read_flags()
         flags |= f_
         nslow += n_
     diag = sim.diagnostics()
+    # FP64 charge density of the resident particles: tiles of the last sort
+    # (LDS) and one thread per particle (no bins)
+    from paper_1310_0930_amd import pic as P
+    rho = torch.zeros(sim.ncell, dtype=torch.float64, device=sim.device)
+    rho_ms = {}
+    for tag, ws in (("tiles", sim.ws.data_ptr()), ("per_particle", None)):
+        P.pic_deposit_rho(sim.ctx, sim._parts, rho.data_ptr(), ws)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(3):
+            P.pic_deposit_rho(sim.ctx, sim._parts, rho.data_ptr(), ws)
+        e1.record()
+        torch.cuda.synchronize()
+        rho_ms[tag] = e0.elapsed_time(e1) / 3
     log(f"{w.name} real={real_bytes}: {total_ms / steps:.3f} ms/step, push {np.mean(push_ms):.3f} ms, "
-        f"slow={nslow} flags={flags}")
+        f"fdtd {np.mean(fdtd_ms):.3f} ms, rho {rho_ms['tiles']:.3f} ms (per particle "
+        f"{rho_ms['per_particle']:.3f}), slow={nslow} flags={flags}")
     return {
         "np": np_total, "ms_per_step": total_ms / steps, "wall_s": wall,
         "push_ms_mean": float(np.mean(push_ms)), "push_ms_median": float(np.median(push_ms)),
+        "fdtd_ms_mean": float(np.mean(fdtd_ms)), "rho_ms": rho_ms,
         "slowpath": int(nslow), "flags": int(flags), "n_alive": int(diag.raw["n_alive"]),
     }
 
@@ -331,7 +349,208 @@ def cpu_baseline(w, log, budget_s=12.0):
             "cpu_model": cpu_model(), "cpus_visible": visible, "cpus_allowed": allowed}
 
 
+# ---------------------------------------------------------------- rocprofv3
+# Summaries of the CSV files rocprofv3 writes for runs of this script
+# (``--output-format csv``), for the text summaries kept under profiles/:
+#
+#   python bench.py summarize trace DIR            kernel times per workload
+#   python bench.py summarize bytes FETCH_DIR WRITE_DIR LOG   HBM bytes per kernel
+#   python bench.py summarize sq DIR LOG           SQ counters of the push/deposit kernel
+#   python bench.py summarize probe DIR            LDS counters of the LDS probe kernels
+#
+# One run covers several workloads; a dispatch is attributed to the workload
+# whose field-advance grid (k_half_b*) comes next for the kernels of a step's
+# start (sort, push) and last before for every other kernel.  LOG is the run's
+# output, whose last line is this script's JSON record (particle counts).
+# ``bytes`` also writes profiles/push_deposit_<workload>_<f32|f64>_counters.json,
+# which bench runs read for ``roofline.traffic`` while the push kernel's
+# sources are unchanged.
+
+_STEP_START = ("k_push", "k_sort", "k_pda", "k_adj_reset", "k_fill_int", "k_scan", "k_tile_starts")
+
+
+def _rp_rows(d, suffix):
+    import csv
+    import glob
+    f = sorted(glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True))
+    if not f:
+        raise SystemExit(f"no *{suffix} under {d}")
+    return list(csv.DictReader(open(f[0])))
+
+
+def _rp_short(name):
+    n = name.replace("void ", "").replace("(anonymous namespace)::", "")
+    if n.startswith("pic::"):
+        return n.split("(")[0]
+    if "at::native" in n:
+        return "torch " + n.split("<")[0]
+    return n.split("(")[0][:60]
+
+
+def _rp_field_grids():
+    """Grid size (threads) of the field-advance launch -> workload name."""
+    out = {}
+    for w in I.WORKLOADS.values():
+        n = w.n3 if w.dims == 3 else (w.n3[0], w.n3[1], 1)
+        ncell = n[0] * n[1] * n[2]
+        col = w.dims == 3 and all(b == 0 for b in w.bc3) and n[2] % 4 == 0
+        blocks = -(-(ncell // 4 if col else ncell) // 256)
+        out.setdefault(str((blocks + 7) // 8 * 8 * 256), w.name)
+    return out
+
+
+def _rp_attribute(disp):
+    """disp: [(dispatch id, kernel name, field grid or None)] in dispatch order."""
+    grids = _rp_field_grids()
+    nxt, last = {}, None
+    for did, name, g in reversed(disp):
+        if g is not None:
+            last = g
+        nxt[did] = last
+    lab, prev = {}, None
+    for did, name, g in disp:
+        if g is not None:
+            prev = g
+        first = nxt[did] if any(t in name for t in _STEP_START) else prev
+        pick = first if first is not None else (nxt[did] if prev is None else prev)
+        lab[did] = grids.get(pick, f"grid {pick}")
+    return lab
+
+
+def _rp_field(r):
+    return (r.get("Grid_Size") or r.get("Grid_Size_X")) if "k_half_b" in r["Kernel_Name"] else None
+
+
+def _rp_counters(d):
+    by, info = {}, {}
+    for r in _rp_rows(d, "counter_collection.csv"):
+        did = int(r["Dispatch_Id"])
+        c = by.setdefault(did, {})
+        c[r["Counter_Name"]] = c.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+        info[did] = r
+    order = sorted(by)
+    lab = _rp_attribute([(i, info[i]["Kernel_Name"], _rp_field(info[i])) for i in order])
+    return [(i, info[i]["Kernel_Name"], by[i], lab[i]) for i in order]
+
+
+def _rp_record(log):
+    for line in reversed(open(log).read().splitlines()):
+        if line.startswith("{"):
+            return json.loads(line)
+    raise SystemExit(f"no JSON record in {log}")
+
+
+def _rp_particles(rec):
+    out = {rec["config"]["workload"]: rec["config"]["particles"]}
+    if "one_gpu_share" in rec:
+        out[rec["one_gpu_share"]["workload"]] = rec["one_gpu_share"]["particles"]
+    return out
+
+
+def summarize_trace(d):
+    rows = _rp_rows(d, "kernel_trace.csv")
+    rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+    lab = _rp_attribute([(int(r["Dispatch_Id"]), r["Kernel_Name"], _rp_field(r)) for r in rows])
+    agg = {}
+    for r in rows:
+        key = (lab[int(r["Dispatch_Id"])], _rp_short(r["Kernel_Name"]))
+        agg.setdefault(key, []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    for w in sorted({k[0] for k in agg}):
+        items = sorted(((sum(v), n, v) for (ww, n), v in agg.items() if ww == w), reverse=True)
+        tot = sum(t for t, _, _ in items)
+        print(f"## {w}: {tot / 1e3:.3f} ms of kernel time")
+        print(f"  {'kernel':56s} {'calls':>6s} {'avg_us':>10s} {'total_ms':>10s} {'pct':>6s}")
+        for t, n, v in items:
+            if t >= 5e-4 * tot:
+                print(f"  {n:56s} {len(v):6d} {t / len(v):10.2f} {t / 1e3:10.3f} {100 * t / tot:6.2f}")
+
+
+def summarize_bytes(dfetch, dwrite, log):
+    rec = _rp_record(log)
+    nps = _rp_particles(rec)
+    per = {}
+    for tag, d in (("FETCH_SIZE", dfetch), ("WRITE_SIZE", dwrite)):
+        disp = _rp_counters(d)
+        # --calibrate-copy: the run's first three copies, 1 GiB each
+        cal = [c[tag] for _, n, c, _ in disp if "copyBuffer" in n][:3]
+        scale = (1 << 20) / (sum(cal) / len(cal))
+        print(f"# {tag}: the three 1 GiB calibration copies read {', '.join('%.1f' % x for x in cal)} KiB "
+              f"-> scale {scale:.4f}")
+        for _, n, c, w in disp:
+            if n.startswith("void pic::") or n.startswith("pic::"):
+                per.setdefault((w, _rp_short(n)), {}).setdefault(tag, []).append(c[tag])
+        per[("scale", tag)] = scale
+    fs, ws_ = per.pop(("scale", "FETCH_SIZE")), per.pop(("scale", "WRITE_SIZE"))
+    print(f"# traffic = FETCH_SIZE x {fs:.4f} + WRITE_SIZE x {ws_:.4f} (KiB per dispatch, mean)")
+    khash = kernel_hash()
+    for (w, n), v in sorted(per.items()):
+        f = float(np.mean(v.get("FETCH_SIZE", [0.0])))
+        wr = float(np.mean(v.get("WRITE_SIZE", [0.0])))
+        t = (f * fs + wr * ws_) * 1024
+        line = (f"  {w:26s} {n:44s} FETCH {f:12.1f} WRITE {wr:12.1f} KiB "
+                f"({len(v.get('FETCH_SIZE', []))} dispatches)  {t / 1e6:10.1f} MB")
+        if "k_push_tile" in n and w in nps:
+            rb = 8 if "double" in n else 4
+            ab = algorithmic_bytes(I.WORKLOADS[w], nps[w], rb)
+            line += f"  algorithmic {ab / 1e6:.1f} MB, ratio {t / ab:.3f}"
+            real = "f64" if rb == 8 else "f32"
+            json.dump({"kernel": "k_push_tile", "workload": w, "real": real, "kernel_hash": khash,
+                       "fetch_kib": f, "write_kib": wr, "fetch_scale": fs, "write_scale": ws_,
+                       "traffic_bytes": int(t), "algorithmic_bytes": ab,
+                       "source": "profiles/hbm_bytes_" + "_".join(sorted(nps)) + ".txt"},
+                      open(os.path.join(ROOT, "profiles", f"push_deposit_{w}_{real}_counters.json"), "w"),
+                      indent=1)
+        print(line)
+
+
+def summarize_sq(d, log):
+    nps = _rp_particles(_rp_record(log))
+    agg = {}
+    for _, n, c, w in _rp_counters(d):
+        if "k_push_tile" in n:
+            a = agg.setdefault((w, _rp_short(n)), {})
+            for k, v in c.items():
+                a.setdefault(k, []).append(v)
+    for (w, n), a in sorted(agg.items()):
+        nb = nps[w] / 64
+        print(f"  {w} {n}: per dispatch, and per batch of 64 particles ({nb:.0f} batches)")
+        for k, v in sorted(a.items()):
+            print(f"    {k:22s} {np.mean(v):16.0f} {np.mean(v) / nb:10.1f}")
+        if a.get("SQ_LDS_IDX_ACTIVE"):
+            print(f"    bank-conflict cycles / LDS-active cycles {sum(a['SQ_LDS_BANK_CONFLICT']) / sum(a['SQ_LDS_IDX_ACTIVE']):.3f}")
+        if a.get("SQ_INSTS_VALU") and a.get("SQ_BUSY_CYCLES"):
+            pass
+
+
+def summarize_probe(d, strides=(1, 2, 4, 8, 16, 32, 64, 128), reps=3):
+    """The --lds-probe run: the first `reps` dispatches are ds_add_u64 at
+    stride 1 (the push's LDS peak), then every op of PROBE_OPS at every
+    stride, `reps` each, in that order."""
+    disp = [x for x in _rp_counters(d) if "k_lds_rate" in x[1]]
+    names = {v: k for k, v in PROBE_OPS.items()}
+    body = disp[reps:]
+    print(f"  {'op':22s} {'stride':>6s} {'LDS instr/op':>12s} {'active cyc/instr':>16s} "
+          f"{'conflict cyc/instr':>18s} {'VALU/op':>8s}")
+    for i, op in enumerate(sorted(names)):
+        for j, st in enumerate(strides):
+            grp = body[(i * len(strides) + j) * reps:(i * len(strides) + j + 1) * reps]
+            c = grp[0][2]
+            ops = c["SQ_WAVES"] * 2048  # iterations per wavefront of the probe (iters=2048)
+            print(f"  {names[op]:22s} {st:6d} {c['SQ_INSTS_LDS'] / ops:12.3f} "
+                  f"{c['SQ_LDS_IDX_ACTIVE'] / c['SQ_INSTS_LDS']:16.2f} "
+                  f"{c['SQ_LDS_BANK_CONFLICT'] / c['SQ_INSTS_LDS']:18.2f} {c['SQ_INSTS_VALU'] / ops:8.3f}")
+
+
+def summarize(argv):
+    kind, rest = argv[0], argv[1:]
+    {"trace": summarize_trace, "bytes": summarize_bytes, "sq": summarize_sq,
+     "probe": summarize_probe}[kind](*rest)
+
+
 def main():
+    if len(sys.argv) > 1 and sys.argv[1] == "summarize":
+        summarize(sys.argv[2:])
+        return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
@@ -403,6 +622,8 @@ def main():
                    "dt": w.dt, "sort_every": w.sort_every, "boundaries": list(w.bc3),
                    "parallelism": "single GPU"},
         "push_deposit_pushes_per_s": r32["np"] / (r32["push_ms_mean"] * 1e-3),
+        "field_advance_ms": round(r32["fdtd_ms_mean"], 5),
+        "rho_deposit_fp64_ms": {k: round(v, 4) for k, v in r32["rho_ms"].items()},
         "roofline": roof(r32, 4, "f32"),
         "lds_atomics": lds_atomics(w, r32["np"], r32["push_ms_mean"], 4),
         "slowpath_pushes": r32["slowpath"], "device_flags": r32["flags"],
@@ -423,20 +644,23 @@ def main():
                "order": ws_.order, "particles": s32["np"], "dt": ws_.dt,
                "sort_every": ws_.sort_every, "steps": k5, "warmup": 3}
 
-        def share(r, rb):
+        def share(r, rb, real):
             ab = algorithmic_bytes(ws_, r["np"], rb)
             return {"value": r["np"] / (r["ms_per_step"] * 1e-3),
                     "ms_per_step": round(r["ms_per_step"], 5),
                     "push_deposit_pushes_per_s": r["np"] / (r["push_ms_mean"] * 1e-3),
                     "push_ms": round(r["push_ms_mean"], 5),
+                    "field_advance_ms": round(r["fdtd_ms_mean"], 5),
+                    "rho_deposit_fp64_ms": {k: round(v, 4) for k, v in r["rho_ms"].items()},
                     "roofline": {"bound": "hbm", "achieved": round(ab / (r["push_ms_mean"] * 1e-3) / 1e9, 2),
                                  "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                  "frac": round(ab / (r["push_ms_mean"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                                 "traffic": traffic_from_profile(ws_.name, real),
                                  "alg_bytes_per_launch": ab},
                     "slowpath_pushes": r["slowpath"], "device_flags": r["flags"]}
-        rec["f32"] = share(s32, 4)
+        rec["f32"] = share(s32, 4, "f32")
         if s64:
-            rec["f64"] = share(s64, 8)
+            rec["f64"] = share(s64, 8, "f64")
         out["one_gpu_share"] = rec
     if a.lds_probe:
         out["lds_probe"] = {"unit": "G lane-ops/s", "rates_by_stride": lds_probe_table()}

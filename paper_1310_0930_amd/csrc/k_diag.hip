@@ -95,6 +95,101 @@ __global__ void k_deposit_rho(DiagParams P, const int* __restrict__ cell, const 
   }
 }
 
+// The same charge density for particles binned by the last sort, one
+// workgroup per tile: the tile's charges are summed in an LDS region (the
+// tile, the push's drift allowance around it and the stencil reach) with
+// double-precision LDS atomics and added to rho once per region node, so
+// the global atomics fall from (n+1)^D per particle to one per region node.
+// Particles that drifted beyond the allowance add to rho directly.
+struct RhoTiles {
+  int ntile[3];
+  const int* starts;  // tile t holds particles starts[t] .. starts[t+1]-1
+};
+
+template <int DIMS, int ORDER, typename R>
+__global__ void __launch_bounds__(256) k_rho_tile(DiagParams P, RhoTiles Tl,
+                                                  const int* __restrict__ cell, const R* o0,
+                                                  const R* o1, const R* o2, const R* q, double qc,
+                                                  double* __restrict__ rho) {
+  using G = Geo<DIMS, ORDER, R>;
+  // nodes a particle reaches relative to its cell: LO .. HI
+  constexpr int LO = -(ORDER / 2), HI = ORDER / 2 + 1;
+  constexpr int RX = G::T + 2 * G::A + ORDER + 1;
+  constexpr int RZ = DIMS == 3 ? G::TZ + 2 * G::AZ + ORDER + 1 : 1;
+  static_assert(HI - LO <= ORDER + 1, "the region holds every node a particle reaches");
+  __shared__ double reg[RX * RX * RZ];
+  const int t = blockIdx.x;
+  const int beg = Tl.starts[t], end = Tl.starts[t + 1];
+  if (beg == end) return;
+  const int org[3] = {(t % Tl.ntile[0]) * G::T, ((t / Tl.ntile[0]) % Tl.ntile[1]) * G::T,
+                      DIMS == 3 ? (t / (Tl.ntile[0] * Tl.ntile[1])) * G::TZ : 0};
+  const int rlo[3] = {org[0] - G::A + LO, org[1] - G::A + LO, DIMS == 3 ? org[2] - G::AZ + LO : 0};
+  for (int r = threadIdx.x; r < RX * RX * RZ; r += blockDim.x) reg[r] = 0.0;
+  __syncthreads();
+  const R* off[3] = {o0, o1, o2};
+  constexpr int M = ORDER + 1;
+  constexpr int MZ = DIMS == 3 ? M : 1;
+  for (int p = beg + threadIdx.x; p < end; p += blockDim.x) {
+    const int cl = cell[p];
+    if (cl < 0 || cl >= P.ncell) continue;
+    const double qp = q ? (double)q[p] : qc;
+    const uint32_t rest = P.dn0.div((uint32_t)cl);
+    int c3[3];
+    c3[0] = cl - (int)rest * P.n[0];
+    c3[1] = DIMS == 3 ? (int)(rest - P.dn1.div(rest) * P.n[1]) : (int)rest;
+    c3[2] = DIMS == 3 ? (int)P.dn1.div(rest) : 0;
+    double w[3][M];
+    int b[3] = {0, 0, 0};
+    bool ok = true;
+    for (int d = 0; d < DIMS; ++d) {
+      const double o = (double)off[d][p];
+      ok = ok && o >= 0.0 && o < 1.0;
+      if (ok) b[d] = node_weights<ORDER>(o, w[d]);
+    }
+    if (!ok) continue;
+    if (DIMS == 2) w[2][0] = 1.0;
+    // cell relative to the tile (periodic image inside the allowance)
+    int l[3] = {0, 0, 0};
+    bool inside = true;
+    for (int d = 0; d < DIMS; ++d) {
+      const int Td = d == 2 ? G::TZ : G::T, Ad = d == 2 ? G::AZ : G::A;
+      int v = c3[d] - org[d];
+      if (!P.open[d]) {
+        v = v < 0 ? v + P.n[d] : v;
+        if (v >= Td + Ad) v -= P.n[d];
+      }
+      l[d] = v;
+      inside = inside && v >= -Ad && v < Td + Ad;
+    }
+    for (int k = 0; k < MZ; ++k)
+      for (int j = 0; j < M; ++j)
+        for (int i = 0; i < M; ++i) {
+          const double v = qp * w[0][i] * w[1][j] * w[2][k];
+          if (inside) {
+            const int rx = l[0] + G::A - LO + b[0] + i;
+            const int ry = l[1] + G::A - LO + b[1] + j;
+            const int rz = DIMS == 3 ? l[2] + G::AZ - LO + b[2] + k : 0;
+            atomicAdd(&reg[(rz * RX + ry) * RX + rx], v);
+          } else {
+            const int iz = DIMS == 3 ? axis_slot(c3[2] + b[2] + k, P.n[2], P.open[2], 0) : 0;
+            const int iy = axis_slot(c3[1] + b[1] + j, P.n[1], P.open[1], 0);
+            const int ix = axis_slot(c3[0] + b[0] + i, P.n[0], P.open[0], 0);
+            if (ix >= 0 && iy >= 0 && iz >= 0) atomicAdd(&rho[ix + P.n[0] * (iy + P.n[1] * iz)], v);
+          }
+        }
+  }
+  __syncthreads();
+  for (int r = threadIdx.x; r < RX * RX * RZ; r += blockDim.x) {
+    const double v = reg[r];
+    if (v == 0.0) continue;
+    const int rx = r % RX, ry = (r / RX) % RX, rz = r / (RX * RX);
+    const int ix = axis_slot(rlo[0] + rx, P.n[0], P.open[0], 0);
+    const int iy = axis_slot(rlo[1] + ry, P.n[1], P.open[1], 0);
+    const int iz = DIMS == 3 ? axis_slot(rlo[2] + rz, P.n[2], P.open[2], 0) : 0;
+    if (ix >= 0 && iy >= 0 && iz >= 0) atomicAdd(&rho[ix + P.n[0] * (iy + P.n[1] * iz)], v);
+  }
+}
+
 // Per-block partials: [max|G|, max|rho|, sum C^2, max|C|, sum drho^2, sum E^2+B^2, -, -]
 constexpr int NPART = 8;
 
@@ -233,17 +328,34 @@ static DiagParams diag_params(const pic_ctx* ctx) {
 }
 
 template <int DIMS, int ORDER, typename R>
-static void rho_t(const DiagParams& P, const pic_particles* p, double qc, double* rho, hipStream_t s) {
+static void rho_t(const DiagParams& P, const pic_particles* p, double qc, double* rho,
+                  const RhoTiles* tiles, int ntiles, hipStream_t s) {
   const long np = p->np;
   if (np == 0) return;
+  if (tiles) {
+    k_rho_tile<DIMS, ORDER, R><<<dim3((unsigned)ntiles), dim3(256), 0, s>>>(
+        P, *tiles, p->cell, (const R*)p->off[0], (const R*)p->off[1], (const R*)p->off[2],
+        (const R*)p->q, qc, rho);
+    return;
+  }
   k_deposit_rho<DIMS, ORDER, R><<<dim3((unsigned)((np + 255) / 256)), dim3(256), 0, s>>>(
       P, p->cell, (const R*)p->off[0], (const R*)p->off[1], (const R*)p->off[2], (const R*)p->q, qc,
       np, rho);
 }
 
-int launch_deposit_rho(const pic_ctx* ctx, const pic_particles* p, double* rho, void* /*ws*/,
+int launch_deposit_rho(const pic_ctx* ctx, const pic_particles* p, double* rho, void* ws,
                        hipStream_t s, bool accumulate) {
   DiagParams P = diag_params(ctx);
+  // the tile kernel needs the bins of a sort of these very arrays in this
+  // workspace (the particles may have moved since)
+  RhoTiles T;
+  const bool binned = ws && ctx->sorted_cell == p->cell && ctx->sorted_ws == ws &&
+                      ctx->sorted_np == p->np;
+  if (binned) {
+    for (int d = 0; d < 3; ++d) T.ntile[d] = ctx->ntile[d];
+    T.starts = (const int*)((const char*)ws + ws_layout(ctx, p->np).starts);
+  }
+  const RhoTiles* tiles = binned ? &T : nullptr;
   if (!accumulate)
     k_fill_d<<<dim3((unsigned)((P.ncell + 255) / 256 < 4096 ? (P.ncell + 255) / 256 : 4096)),
                dim3(256), 0, s>>>(rho, P.ncell);
@@ -253,9 +365,9 @@ int launch_deposit_rho(const pic_ctx* ctx, const pic_particles* p, double* rho, 
 #define PIC_RHO(DD, OO)                                              \
   if (D == DD && O == OO) {                                          \
     if (dbl)                                                         \
-      rho_t<DD, OO, double>(P, p, qc, rho, s);                       \
+      rho_t<DD, OO, double>(P, p, qc, rho, tiles, ctx->ntiles, s);   \
     else                                                             \
-      rho_t<DD, OO, float>(P, p, qc, rho, s);                        \
+      rho_t<DD, OO, float>(P, p, qc, rho, tiles, ctx->ntiles, s);    \
   }
   PIC_RHO(2, 1) PIC_RHO(2, 2) PIC_RHO(2, 3) PIC_RHO(2, 4)
   PIC_RHO(3, 1) PIC_RHO(3, 2) PIC_RHO(3, 3) PIC_RHO(3, 4)

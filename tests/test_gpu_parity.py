@@ -12,7 +12,7 @@ import pytest
 import oracle as O
 from paper_1310_0930_amd import inputs as I
 
-from _parity import TOL, compare, gpu_sim, inputs_for, oracle_state, oracle_threads, say
+from _parity import TOL, compare, gpu_sim, inputs_for, oracle_config, oracle_state, oracle_threads, say
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -196,6 +196,47 @@ def test_diagnostics_match_oracle(rb):
     wf, wk = ref.energies()
     assert abs(d1.raw["w_field"] - wf) <= (1e-10 if rb == 8 else 1e-4) * wf
     assert abs(d1.raw["w_kin"] - wk) <= (1e-10 if rb == 8 else 1e-5) * wk
+
+
+@pytest.mark.parametrize("dims,order,rb,bc", [(3, 2, 4, (0, 0, 0)), (3, 2, 8, (0, 1, 0)),
+                                               (3, 3, 4, (0, 1, 1)), (3, 4, 8, (1, 0, 0)),
+                                               (2, 2, 4, (0, 1)), (2, 4, 8, (1, 1))])
+def test_rho_tiles_match_oracle(dims, order, rb, bc):
+    """FP64 charge density of particles binned by the last sort (LDS tiles,
+    global atomics for particles beyond the drift allowance) and of the same
+    particles without bins (one thread per particle) equal the oracle's
+    deposit of the stored positions, pushed after the sort until some hot
+    particles have drifted beyond the allowance."""
+    from paper_1310_0930_amd import pic as P
+    n = (20, 18, 13) if dims == 3 else (40, 36)
+    w = I.Workload("w_rho", dims, n, (0.2,) * dims, order, 3, 0.6, 1, bc=bc,
+                   seed=I.SEED_BASE + 140 + 10 * dims + order)
+    pl, E, B = inputs_for(w)
+    sim = gpu_sim(w, rb, pl, E, B, sort_every=1 << 20)
+    sim.sort()
+    nslow = 0
+    for _ in range(24):  # push until some particles have drifted beyond the allowance
+        sim.push_deposit()
+        sim.field_advance()
+        _, nslow = sim.read_flags()
+        if nslow > 0:
+            break
+    assert nslow > 0
+    st = sim.download()
+    Xg, alive = sim.positions(st)
+    q = pl.charges()[st["id"]]
+    ref = O.State(oracle_config(w), Xg, st["u"].T, q, E, B, alive=alive.astype(np.int8))
+    rho_o = ref.rho()
+    r_t = torch.zeros(sim.ncell, dtype=torch.float64, device="cuda")
+    r_g = torch.zeros_like(r_t)
+    P.pic_deposit_rho(sim.ctx, sim._parts, r_t.data_ptr(), sim.ws.data_ptr())
+    P.pic_deposit_rho(sim.ctx, sim._parts, r_g.data_ptr(), None)
+    torch.cuda.synchronize()
+    scale = np.abs(rho_o).max()
+    for name, r in (("tiles", r_t), ("global", r_g)):
+        e = np.abs(r.cpu().numpy().reshape(rho_o.shape) - rho_o).max() / scale
+        say("rho", name, dims, order, rb, bc, e)
+        assert e <= 1e-13, (name, e)
 
 
 def test_fdtd_eigenmode_fp64():
