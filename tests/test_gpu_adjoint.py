@@ -66,8 +66,10 @@ def test_field_advance_adjoint_dot_product(dims, bc, rb, nz):
     assert abs(lhs - rhs) <= (1e-12 if rb == 8 else 1e-5) * (abs(lhs) + 1.0) * 10
 
 
-def _one_step_check(w, rb, seed):
-    """<lam_out, JVP(delta)> (oracle, FP64) vs <VJP(lam_out), delta> (GPU)."""
+def _one_step_check(w, rb, seed, tiled=True):
+    """<lam_out, JVP(delta)> (oracle, FP64) vs <VJP(lam_out), delta> (GPU);
+    tiled=False hands the adjoint a workspace without tile bins (the
+    global-memory kernel for every particle)."""
     from paper_1310_0930_amd import pic as P
     pl, E, B = inputs_for(w)
     D = w.dims
@@ -104,8 +106,9 @@ def _one_step_check(w, rb, seed):
     lf = P.fields_struct(LE, LB, LJ)
     P.pic_field_advance_adjoint(sim.ctx, lf, sim.ws.data_ptr(), sim.stream)
     parts = P.particles_struct(sim.np, state[0], state[1], state[2], sim.q)
+    ws = sim.ws if tiled else torch.zeros_like(sim.ws)
     P.pic_push_deposit_adjoint(sim.ctx, parts, P.fields_struct(state[3], state[4]), lf,
-                               P.particles_struct(sim.np, None, LX, LU), sim.ws.data_ptr(), sim.stream)
+                               P.particles_struct(sim.np, None, LX, LU), ws.data_ptr(), sim.stream)
     torch.cuda.synchronize()
     gX = np.zeros((npart, 3))
     gu = np.zeros((npart, 3))
@@ -123,6 +126,21 @@ def test_step_adjoint_matches_oracle_jvp_3d(order):
     w = I.Workload("adj3", 3, (12, 10, 9), (0.2, 0.25, 0.2), order, 4, 0.3, 1,
                    seed=I.SEED_BASE + 90 + order)
     lhs, rhs = _one_step_check(w, 8, 11 + order)
+    assert abs(lhs - rhs) <= 1e-10 * abs(lhs)
+
+
+@pytest.mark.parametrize("tiled", [True, False])
+@pytest.mark.parametrize("bc", [(0, 1, 0), (0, 0, 1), (1, 1, 1)])
+@pytest.mark.parametrize("order", [1, 2, 3, 4])
+def test_step_adjoint_matches_oracle_jvp_3d_open_faces(order, bc, tiled):
+    """One 3D step's adjoint against the oracle's JVP with an open y face, an
+    open z face (the axis the LDS slabs cut), and every face open; z has a
+    ragged last tile.  tiled: sorted particles with their tile bins (LDS
+    tiles or z slabs, off-allowance particles through the global kernel);
+    otherwise every particle in the global-memory kernel."""
+    w = I.Workload("adj3o", 3, (12, 10, 9), (0.2, 0.25, 0.2), order, 4, 0.3, 1, bc=bc,
+                   ramp_cells=3.0, seed=I.SEED_BASE + 150 + order + 4 * sum(bc))
+    lhs, rhs = _one_step_check(w, 8, 61 + order + 7 * bc[2], tiled=tiled)
     assert abs(lhs - rhs) <= 1e-10 * abs(lhs)
 
 
@@ -263,25 +281,30 @@ def _tiled_vs_global(w, rb, seed, shuffled_too=True):
             assert np.abs(mixed[k] - b).max() <= tol * scale, name
 
 
-@pytest.mark.parametrize("dims,rb,order", [(2, 8, 2), (2, 4, 2), (2, 8, 3), (3, 8, 1), (3, 4, 1),
-                                           (3, 8, 2), (3, 4, 2), (3, 4, 3), (3, 8, 4), (3, 4, 4)])
-def test_tiled_step_adjoint_equals_global_memory_adjoint(dims, rb, order):
+@pytest.mark.parametrize("dims,rb,order,bc", [
+    (2, 8, 2, (0, 1)), (2, 4, 2, (0, 1)), (2, 8, 3, (0, 1)),
+    (3, 8, 1, (0, 1, 0)), (3, 4, 1, (0, 1, 0)), (3, 8, 2, (0, 1, 0)), (3, 4, 2, (0, 1, 0)),
+    (3, 4, 3, (0, 1, 0)), (3, 8, 4, (0, 1, 0)), (3, 4, 4, (0, 1, 0)),
+    (3, 8, 1, (0, 1, 1)), (3, 4, 1, (0, 1, 1)), (3, 8, 2, (0, 1, 1)), (3, 4, 2, (0, 1, 1)),
+    (3, 4, 3, (0, 1, 1)), (3, 8, 4, (0, 1, 1)), (3, 4, 4, (0, 1, 1))])
+def test_tiled_step_adjoint_equals_global_memory_adjoint(dims, rb, order, bc):
     """The step adjoint runs out of LDS when the context holds tile bins for
     the particles (same count, same workspace), else one thread per particle
     in global memory.  In 3D a tile is cut into z slabs (one per workgroup)
     where its regions exceed a CU's LDS: 2 slabs for quadratic FP32 and
     linear FP64, 4 for cubic FP32 and quadratic FP64, one-cell slabs for
     quartic FP32 (linear FP32 and quartic FP64 take whole tiles); the 3D
-    grid here has a ragged last tile along z and an open face.  Both paths
+    grid here has a ragged last tile along z and an open y face, or open y
+    and z faces (slabs next to the open z face).  Both paths
     must give the same lamX, lamU, lamE, lamB, also for particles in an
     order other than the sort's."""
     if dims == 2:
         lz = I.Laser(a0=2.0, omega0=4.0, waist=1.0, tau=0.4, x_center=1.2)
-        w = I.Workload("adjt", 2, (48, 32), (0.1, 0.2), order, 6, 0.2, 1, bc=(0, 1),
+        w = I.Workload("adjt", 2, (48, 32), (0.1, 0.2), order, 6, 0.2, 1, bc=bc,
                        ramp_cells=6.0, laser=lz, seed=I.SEED_BASE + 120 + order)
     else:
         w = I.Workload("adjt3", 3, (24, 16, 20), (0.2, 0.25, 0.2), order, 4, 0.3, 1,
-                       bc=(0, 1, 0), ramp_cells=4.0, seed=I.SEED_BASE + 130 + order)
+                       bc=bc, ramp_cells=4.0, seed=I.SEED_BASE + 130 + order)
     _tiled_vs_global(w, rb, 31 + order)
 
 
