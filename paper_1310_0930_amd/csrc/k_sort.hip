@@ -1,31 +1,26 @@
 // Tile sort of the SoA particle arrays, in two levels: a counting sort on
 // the tile of the particle's cell (absorbed particles go to a last, dead
 // bin, which is dropped: the live particles are compacted to the front),
-// then, inside every tile, a placement by (class, rank within the cell and
-// class, cell).
+// then, inside every tile, a placement by class and bank residue.
 //
 // Not a step of the paper's method: it is the data layout that makes the
 // fused push/deposit local (one workgroup per tile, fields and currents in
 // LDS), the GPU counterpart of the paper's per-node particle partition
 // (Sec. 3) and of its answer to deposit write conflicts (Sec. 3.1, Sec. 5.2).
 //
-// Inside a tile the particles come class by class and, within a class,
-// rank by rank: first one particle of every cell that has one in that
-// class (in cell order), then a second one, and so on.  The class is the
-// half of the cell the particle sits in along each axis (offset >= 1/2 or
-// not), which fixes the first stencil node of every field and current
-// component relative to the cell; so a wavefront's 64 lanes sit in
-// neighbouring, distinct cells with the same stencil shape, and their LDS
-// reads and atomics spread over the banks instead of colliding where
-// neighbouring lanes' stencils are shifted by one node against each other.
-// The tile-level pass aggregates runs of equal tiles inside a wavefront
-// (particles stay in their tile for many steps), one global atomic per run;
-// the placement runs in LDS, one workgroup per tile.
+// Inside a tile the particles come class by class.  The class is the half
+// of the cell the particle sits in along each axis (offset >= 1/2 or not),
+// which fixes the first stencil node of every field and current component
+// relative to the cell, so that the 64 lanes of a wavefront read and add at
+// their cells' bases plus one common offset.  Within a class the particles
+// cycle through the LDS bank residues of their cells (k_sort_place), so that
+// those bases fall on distinct banks.  The tile-level pass aggregates runs
+// of equal tiles inside a wavefront (particles stay in their tile for many
+// steps), one global atomic per run; the placement runs in LDS, one
+// workgroup per tile.
 #include "k_common.h"
 
 namespace pic {
-
-constexpr int NB = SORT_BINS;
 
 struct SortParams {
   int n[3];
@@ -283,18 +278,22 @@ struct PVal {
 
 // Bank residues of a tile's cells.  In the push every LDS access of a
 // wavefront is the lanes' cell base addresses plus one offset common to
-// the lanes of one class (one stencil shape).  The LDS serves a wavefront
-// 16 lanes at a time from 32 four-byte banks, and the current tile's
-// 8-byte atomics (and the double-precision field reads) take two banks
-// each: 16 lanes go through without conflict when their cells' element
-// indices in the current region differ modulo 16 (the residue; the
-// single-precision field reads, one bank each, then differ modulo 32 as
-// well where the two regions share their strides).  One workgroup lists the
-// tile's cells by residue: order[0 .. ncells) = cells sorted by (residue,
-// cell), order[TILE_CELLS_MAX + r] = first entry of residue r (r <= RES).
-constexpr int RES = 16;
+// the lanes of one class (one stencil shape).  The LDS has 32 four-byte
+// banks and serves a wavefront's 4-byte accesses 32 lanes per cycle and its
+// 8-byte accesses (the current tile's atomics, the double-precision field
+// reads) 16 lanes per cycle, two banks each.  Lanes in one such group go
+// through without conflict when their cells' element indices in the current
+// region differ modulo the group size; 32 consecutive distinct residues
+// modulo 32 are also 16 distinct residues modulo 16 in each half, so the
+// residue is taken modulo 32 in both precisions (replayed access patterns:
+// modulo 16 costs the double-precision gather and deposit 18 % more LDS
+// cycles).  The field and current regions share their strides at the
+// benchmark orders.  One workgroup lists the tile's cells by residue:
+// order[0 .. ncells) = cells sorted by (residue, cell),
+// order[TILE_CELLS_MAX + r] = first entry of residue r (r <= RES).
 constexpr int ORDER_NT = 512;
 constexpr int TILE_CELLS_MAX = 512;
+constexpr int RES = 32;
 __device__ __forceinline__ int cell_residue(const SortParams& S, int lc) {
   const int lx = lc % S.T[0], ly = (lc / S.T[0]) % S.T[1], lz = lc / (S.T[0] * S.T[1]);
   return (lx + S.rs1 * ly + S.rs2 * lz) % RES;
@@ -329,15 +328,15 @@ __global__ void __launch_bounds__(ORDER_NT) k_sort_order(SortParams S, int* __re
 
 // Placement of one tile's particles (one workgroup per tile) from the
 // scatter's copy back into the particle arrays.  Pass 1 gives every particle
-// its class and its rank within (cell, class) from LDS counters; the tile's
-// NB bins are (class, min(rank, last bucket)).  In a bin below the class's
-// last rank bucket every cell appears once; its cells are ranked by (k, r)
-// with r the cell's residue and k the number of the bin's cells of the same
-// residue before it (in cell order): the bin cycles through the residues it
-// holds, so every 16 consecutive lanes of a full cycle fall on distinct
-// banks.  One thread per (class, residue) walks that residue's cells to find
-// k for every rank level; pass 2 puts each particle at its bin's start plus
-// its rank in the bin.  The last bucket is filled in arrival order.
+// its class and its rank among the particles of its (cell, class), from LDS
+// counters.  Within a class the particles are ranked by (k, r): r is the
+// residue of the particle's cell, k the number of the class's particles of
+// the same residue before it (cells in cell order, a cell's particles in
+// rank order).  The class cycles through the residues it holds, so any RES
+// consecutive lanes of a full cycle fall on distinct banks, and particles of
+// one cell sit a whole cycle apart.  One thread per (class, residue) walks
+// that residue's cells for the first k of every cell; pass 2 puts each
+// particle at its class's start plus its rank in the class.
 constexpr int PLACE_NT = 512;
 constexpr int PLACE_SRC_MAX = 8192;
 template <typename R>
@@ -345,11 +344,11 @@ __global__ void __launch_bounds__(PLACE_NT) k_sort_place(SortArrays<R> A, SortPa
                                                           const int* __restrict__ tstart,
                                                           const int* __restrict__ order,
                                                           int* __restrict__ scratch, int dims) {
-  __shared__ int cnt[TILE_CELLS_MAX * 8];        // particles per (class, cell)
-  __shared__ unsigned char kk[NB][TILE_CELLS_MAX];  // k of a cell in a bin
-  __shared__ int cntb[NB][RES];                  // cells per (bin, residue)
-  __shared__ int binc[NB];
-  __shared__ int bin0[NB];
+  constexpr int NC = 8;                           // classes (2^dims)
+  __shared__ int cnt[NC * TILE_CELLS_MAX];        // particles per (class, cell)
+  __shared__ int kb[NC * TILE_CELLS_MAX];         // k of the first of them
+  __shared__ int cntr[NC][RES];                   // particles per (class, residue)
+  __shared__ int cls0[NC + 1];                    // first slot of each class
   __shared__ int ord[TILE_CELLS_MAX + RES + 1];
   __shared__ unsigned char res[TILE_CELLS_MAX];
   __shared__ int src[PLACE_SRC_MAX];  // source of each slot of the tile
@@ -362,13 +361,11 @@ __global__ void __launch_bounds__(PLACE_NT) k_sort_place(SortArrays<R> A, SortPa
     res[i] = (unsigned char)cell_residue(S, i);
   }
   for (int i = threadIdx.x; i <= RES; i += PLACE_NT) ord[TILE_CELLS_MAX + i] = order[TILE_CELLS_MAX + i];
-  for (int i = threadIdx.x; i < TILE_CELLS_MAX * 8; i += PLACE_NT) cnt[i] = 0;
-  for (int i = threadIdx.x; i < NB; i += PLACE_NT) binc[i] = 0;
+  for (int i = threadIdx.x; i < NC * TILE_CELLS_MAX; i += PLACE_NT) cnt[i] = 0;
   __syncthreads();
   const int tx = t % S.ntile[0], ty = (t / S.ntile[0]) % S.ntile[1], tz = t / (S.ntile[0] * S.ntile[1]);
-  const int rb = NB >> dims;  // rank buckets per class
   // pass 1: class and rank of every particle (batches of PB1 per thread,
-  // all loads of a batch in flight together)
+  // all loads of a batch in flight together); scratch = rank, class, cell
   constexpr int PB1 = 4;
   for (int i0 = beg + threadIdx.x; i0 < end; i0 += PB1 * PLACE_NT) {
     int pc[PB1];
@@ -402,47 +399,34 @@ __global__ void __launch_bounds__(PLACE_NT) k_sort_place(SortArrays<R> A, SortPa
             (cx - tx * S.T[0]) + S.T[0] * ((cy - ty * S.T[1]) + S.T[1] * (cz - tz * S.T[2]));
         int cls = (po[k][0] >= R(0.5) ? 1 : 0) | (po[k][1] >= R(0.5) ? 2 : 0);
         if (dims == 3) cls |= po[k][2] >= R(0.5) ? 4 : 0;
-        const int rank = atomicAdd(&cnt[cls * TILE_CELLS_MAX + cell], 1);
-        scratch[i] = (cls * rb + min(rank, rb - 1)) * TILE_CELLS_MAX + cell;
+        const int key = cls * TILE_CELLS_MAX + cell;
+        const int rank = atomicAdd(&cnt[key], 1);
+        scratch[i] = (rank << 12) | key;
       }
     }
   }
   __syncthreads();
-  // k of every cell in every bin below the last bucket, the bins' residue
-  // counts, and the last buckets' sizes: one thread per (class, residue)
-  if (threadIdx.x < (1 << dims) * RES) {
+  // first k of every (class, cell) and the (class, residue) totals: one
+  // thread per (class, residue) walks the residue's cells in cell order
+  const int ncls = 1 << dims;
+  if (threadIdx.x < ncls * RES) {
     const int cls = threadIdx.x / RES, r = threadIdx.x % RES;
-    constexpr int MR = NB / 4 - 1;  // rb - 1 <= MR rank levels (rb = NB / 2^dims, dims >= 2)
-    int k[MR];
-#pragma unroll
-    for (int lv = 0; lv < MR; ++lv) k[lv] = 0;
-    int last = 0;
+    int k = 0;
     for (int i = ord[TILE_CELLS_MAX + r]; i < ord[TILE_CELLS_MAX + r + 1]; ++i) {
-      const int c = ord[i];
-      const int n = cnt[cls * TILE_CELLS_MAX + c];
-#pragma unroll
-      for (int lv = 0; lv < MR; ++lv)
-        if (lv < rb - 1 && n > lv) kk[cls * rb + lv][c] = (unsigned char)k[lv]++;
-      last += max(0, n - (rb - 1));
+      const int key = cls * TILE_CELLS_MAX + ord[i];
+      kb[key] = k;
+      k += cnt[key];
     }
-#pragma unroll
-    for (int lv = 0; lv < MR; ++lv)
-      if (lv < rb - 1) cntb[cls * rb + lv][r] = k[lv];
-    if (last) atomicAdd(&binc[cls * rb + rb - 1], last);
-  }
-  __syncthreads();
-  if (threadIdx.x < NB && threadIdx.x % rb < rb - 1) {
-    int acc = 0;
-    for (int r = 0; r < RES; ++r) acc += cntb[threadIdx.x][r];
-    binc[threadIdx.x] = acc;
+    cntr[cls][r] = k;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
     int acc = beg;
-    for (int b = 0; b < NB; ++b) {
-      bin0[b] = acc;
-      acc += binc[b];
+    for (int c = 0; c < ncls; ++c) {
+      cls0[c] = acc;
+      for (int r = 0; r < RES; ++r) acc += cntr[c][r];
     }
+    cls0[ncls] = acc;
   }
   __syncthreads();
   const int n = end - beg;
@@ -453,22 +437,17 @@ __global__ void __launch_bounds__(PLACE_NT) k_sort_place(SortArrays<R> A, SortPa
   // slot (gathered loads, coalesced stores); a larger tile stores directly.
   for (int i = beg + threadIdx.x; i < end; i += PLACE_NT) {
     const int v = scratch[i];
-    const int b = v / TILE_CELLS_MAX, lc = v % TILE_CELLS_MAX;
-    int j;
-    if (b % rb < rb - 1) {
-      // rank of (k, r) in the bin: every residue with more than k cells
-      // fills levels 0..k, those below r also level k
-      const int k = kk[b][lc], r = res[lc];
-      int pos = 0;
+    const int key = v & 4095, cls = key / TILE_CELLS_MAX, lc = key % TILE_CELLS_MAX;
+    // rank of (k, r) in the class: every residue with more than k particles
+    // fills levels 0..k, those below r also level k
+    const int k = kb[key] + (v >> 12), r = res[lc];
+    int pos = 0;
 #pragma unroll
-      for (int q = 0; q < RES; ++q) {
-        const int c = cntb[b][q];
-        pos += min(c, k) + (q < r && c > k ? 1 : 0);
-      }
-      j = bin0[b] + pos;
-    } else {
-      j = atomicAdd(&bin0[b], 1);  // last bucket: arrival order
+    for (int q = 0; q < RES; ++q) {
+      const int c = cntr[cls][q];
+      pos += min(c, k) + (q < r && c > k ? 1 : 0);
     }
+    const int j = cls0[cls] + pos;
     if (staged) {
       src[j - beg] = i;
     } else {

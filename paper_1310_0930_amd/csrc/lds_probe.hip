@@ -130,7 +130,8 @@ int lds_probe_run(int op, int stride, int iters, int blocks, void* sink, void* s
 // components, 27 reads each at the component's own stencil); 1: the double
 // one; 2: the single form's current deposit (54 ds_add_u64 of one virtual
 // segment); 3: the double form's (ds_add_f64); 4: the single-precision gather
-// with one ds_read_b32 per value.
+// with one ds_read_b32 per value; 5: the double one with one ds_read_b64 per
+// value.
 namespace {
 
 constexpr int RX = 13, RV = RX * RX * RX;
@@ -138,11 +139,11 @@ constexpr int RX = 13, RV = RX * RX * RX;
 template <int MODE>
 __global__ void __launch_bounds__(NT) k_lds_pattern(const int* __restrict__ lanes, int npat,
                                                     int iters, uint64_t* sink) {
-  // mode 4: the single-precision gather with one 32-bit read per value
-  // (reads through a volatile LDS pointer are not paired into ds_read2)
+  // modes 4, 5: the gather with one read per value (reads through a
+  // volatile LDS pointer are not paired into ds_read2)
   using T = typename std::conditional<MODE == 0 || MODE == 4, float,
             typename std::conditional<MODE == 2, unsigned long long, double>::type>::type;
-  constexpr bool GATHER = MODE < 2 || MODE == 4;
+  constexpr bool GATHER = MODE < 2 || MODE >= 4;
   constexpr int COMPS = GATHER ? 6 : 3;
   __shared__ T lds[COMPS * RV];
   for (int i = threadIdx.x; i < COMPS * RV; i += NT) lds[i] = T(i & 7);
@@ -173,8 +174,8 @@ __global__ void __launch_bounds__(NT) k_lds_pattern(const int* __restrict__ lane
   for (int it = 0; it < iters; ++it) {
 #pragma unroll
     for (int c = 0; c < COMPS; ++c) {
-      if constexpr (MODE == 4) {
-        typedef __attribute__((address_space(3))) const volatile float lf;
+      if constexpr (MODE >= 4) {
+        typedef __attribute__((address_space(3))) const volatile T lf;
         lf* p = (lf*)(lds + base[c]);
 #pragma unroll
         for (int k = 0; k < 3; ++k)
@@ -225,7 +226,7 @@ int launch_pattern(const int* lanes, int npat, int iters, int blocks, uint64_t* 
 
 extern "C" {
 
-/* Replay the push kernel's LDS accesses (mode 0..3, see above) for `iters`
+/* Replay the push kernel's LDS accesses (mode 0..5, see above) for `iters`
  * particle batches per wavefront with the lane layouts `lanes` (device,
  * npat x 64 ints: cell in the 13^3 region, class in bits 16..18; every
  * stencil stays inside the region for cells with coordinates 1..11) and
@@ -233,7 +234,7 @@ extern "C" {
  * -1 for bad arguments. */
 int lds_probe_pattern(int mode, const void* lanes, int npat, int iters, int blocks, void* sink,
                       void* stream, float* ms) {
-  if (mode < 0 || mode > 4 || !lanes || npat < 1 || iters < 1 || blocks < 1 || !sink || !ms)
+  if (mode < 0 || mode > 5 || !lanes || npat < 1 || iters < 1 || blocks < 1 || !sink || !ms)
     return -1;
   hipStream_t s = (hipStream_t)stream;
   hipEvent_t a, b;
@@ -251,7 +252,8 @@ int lds_probe_pattern(int mode, const void* lanes, int npat, int iters, int bloc
       case 1: err = launch_pattern<1>(L, npat, iters, blocks, k, s); break;
       case 2: err = launch_pattern<2>(L, npat, iters, blocks, k, s); break;
       case 3: err = launch_pattern<3>(L, npat, iters, blocks, k, s); break;
-      default: err = launch_pattern<4>(L, npat, iters, blocks, k, s); break;
+      case 4: err = launch_pattern<4>(L, npat, iters, blocks, k, s); break;
+      default: err = launch_pattern<5>(L, npat, iters, blocks, k, s); break;
     }
   }
   if (!err) err = (int)hipEventRecord(b, s);

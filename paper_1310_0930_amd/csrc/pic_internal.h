@@ -138,12 +138,6 @@ struct DevFlags {
 static_assert(sizeof(DevFlags) == 64, "DevFlags layout");
 
 // ------------------------------------------------------------------ workspace
-// Inside a tile the sort orders particles by (class, rank within the cell
-// and class, cell) in SORT_BINS bins: the class of a particle is which half
-// of its cell it sits in along each axis (2^dims classes), with
-// SORT_BINS / 2^dims rank buckets per class.
-constexpr int SORT_BINS = 32;
-
 struct WsLayout {
   size_t flags;      // DevFlags
   size_t starts;     // int32[ntiles + 2]   tile starts (entry ntiles = dead bin start, then np)
