@@ -18,6 +18,8 @@
 // of equal tiles inside a wavefront (particles stay in their tile for many
 // steps), one global atomic per run; the placement runs in LDS, one
 // workgroup per tile.
+#include <type_traits>
+
 #include "k_common.h"
 
 namespace pic {
@@ -337,7 +339,7 @@ __global__ void __launch_bounds__(ORDER_NT) k_sort_order(SortParams S, int* __re
 // one cell sit a whole cycle apart.  One thread per (class, residue) walks
 // that residue's cells for the first k of every cell; pass 2 puts each
 // particle at its class's start plus its rank in the class.
-constexpr int PLACE_NT = 512;
+constexpr int PLACE_NT = 1024;
 constexpr int PLACE_SRC_MAX = 8192;
 template <typename R>
 __global__ void __launch_bounds__(PLACE_NT) k_sort_place(SortArrays<R> A, SortParams S,
@@ -345,8 +347,13 @@ __global__ void __launch_bounds__(PLACE_NT) k_sort_place(SortArrays<R> A, SortPa
                                                           const int* __restrict__ order,
                                                           int* __restrict__ scratch, int dims) {
   constexpr int NC = 8;                           // classes (2^dims)
-  __shared__ int cnt[NC * TILE_CELLS_MAX];        // particles per (class, cell)
-  __shared__ int kb[NC * TILE_CELLS_MAX];         // k of the first of them
+  // counters of passes 1-2, then (pass 3) one particle array of the tile
+  constexpr size_t POOL = 2 * sizeof(int) * NC * TILE_CELLS_MAX > sizeof(R) * PLACE_SRC_MAX
+                              ? 2 * sizeof(int) * NC * TILE_CELLS_MAX
+                              : sizeof(R) * PLACE_SRC_MAX;
+  __shared__ __align__(16) unsigned char pool[POOL];
+  int* const cnt = (int*)pool;                   // particles per (class, cell)
+  int* const kb = cnt + NC * TILE_CELLS_MAX;     // k of the first of them
   __shared__ int cntr[NC][RES];                   // particles per (class, residue)
   __shared__ int cls0[NC + 1];                    // first slot of each class
   __shared__ int ord[TILE_CELLS_MAX + RES + 1];
@@ -431,15 +438,16 @@ __global__ void __launch_bounds__(PLACE_NT) k_sort_place(SortArrays<R> A, SortPa
   __syncthreads();
   const int n = end - beg;
   const bool staged = n <= PLACE_SRC_MAX;
-  // Slots.  Stores to scattered slots cost more than loads from them (each
-  // partial cache-line write is merged in memory), so when the tile fits,
-  // pass 2 records the source of every slot in LDS and pass 3 copies slot by
-  // slot (gathered loads, coalesced stores); a larger tile stores directly.
-  for (int i = beg + threadIdx.x; i < end; i += PLACE_NT) {
-    const int v = scratch[i];
+  // Slots.  When the tile fits, pass 2 records the source of every slot in
+  // LDS and pass 3 moves the particle arrays one at a time through LDS:
+  // coalesced loads of the tile's copy, coalesced stores in slot order
+  // (gathered loads from the copy straight out of memory had each touched a
+  // cache line per lane); a larger tile stores directly.
+  //
+  // Slot of a particle: rank of (k, r) in the class: every residue with more than k particles
+  // fills levels 0..k, those below r also level k
+  auto slot = [&](int v) {
     const int key = v & 4095, cls = key / TILE_CELLS_MAX, lc = key % TILE_CELLS_MAX;
-    // rank of (k, r) in the class: every residue with more than k particles
-    // fills levels 0..k, those below r also level k
     const int k = kb[key] + (v >> 12), r = res[lc];
     int pos = 0;
 #pragma unroll
@@ -447,28 +455,105 @@ __global__ void __launch_bounds__(PLACE_NT) k_sort_place(SortArrays<R> A, SortPa
       const int c = cntr[cls][q];
       pos += min(c, k) + (q < r && c > k ? 1 : 0);
     }
-    const int j = cls0[cls] + pos;
-    if (staged) {
-      src[j - beg] = i;
-    } else {
+    return cls0[cls] + pos;
+  };
+  if (!staged) {
+    for (int i = beg + threadIdx.x; i < end; i += PLACE_NT) {
+      const int j = slot(scratch[i]);
       PVal<R> pv;
       pv.load(A, i, dims);
       pv.store(A, j, dims);
     }
+    return;
   }
-  if (!staged) return;
+  // every thread issues all of its loads before it uses any (few
+  // workgroups per CU: their memory latency is not hidden by others)
+  constexpr int PER = PLACE_SRC_MAX / PLACE_NT;
+  {
+    int v[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int i = beg + threadIdx.x + k * PLACE_NT;
+      if (i < end) v[k] = scratch[i];
+    }
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int i = beg + threadIdx.x + k * PLACE_NT;
+      if (i < end) src[slot(v[k]) - beg] = i;
+    }
+  }
   __syncthreads();
-  // pass 3: batches of PB slots per thread, every load of a batch first
-  constexpr int PB = 4;
-  for (int t0 = threadIdx.x; t0 < n; t0 += PB * PLACE_NT) {
-    PVal<R> pv[PB];
+  // pass 3: the arrays of one element type one after the other through the
+  // pool; the loads of the next array are in flight while the current one
+  // is placed
+  // (`arr(a)` gives array a's destination and copy; a is a compile-time
+  // index after unrolling)
+  auto pipeline = [&](auto arr, int count) {
+    using T = typename std::remove_pointer<decltype(arr(0).first)>::type;
+    constexpr int MAXA = 7;
+    T* stg = (T*)pool;
+    T nx[PER], w[PER];
+    {
+      const T* f = arr(0).second;
 #pragma unroll
-    for (int k = 0; k < PB; ++k)
-      if (t0 + k * PLACE_NT < n) pv[k].load(A, src[t0 + k * PLACE_NT], dims);
+      for (int k = 0; k < PER; ++k) {
+        const int i = threadIdx.x + k * PLACE_NT;
+        if (i < n) nx[k] = f[beg + i];
+      }
+    }
 #pragma unroll
-    for (int k = 0; k < PB; ++k)
-      if (t0 + k * PLACE_NT < n) pv[k].store(A, beg + t0 + k * PLACE_NT, dims);
-  }
+    for (int a = 0; a < MAXA; ++a) {
+      if (a >= count) break;
+#pragma unroll
+      for (int k = 0; k < PER; ++k) {
+        const int i = threadIdx.x + k * PLACE_NT;
+        if (i < n) stg[i] = nx[k];
+      }
+      __syncthreads();
+      if (a + 1 < count) {
+        const T* f = arr(a + 1).second;
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+          const int i = threadIdx.x + k * PLACE_NT;
+          if (i < n) nx[k] = f[beg + i];
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < PER; ++k) {
+        const int j = threadIdx.x + k * PLACE_NT;
+        if (j < n) w[k] = stg[src[j] - beg];
+      }
+      T* d = arr(a).first;
+#pragma unroll
+      for (int k = 0; k < PER; ++k) {
+        const int j = threadIdx.x + k * PLACE_NT;
+        if (j < n) d[beg + j] = w[k];
+      }
+      __syncthreads();
+    }
+  };
+  struct IntArr {
+    int* first;
+    const int* second;
+  };
+  struct RArr {
+    R* first;
+    const R* second;
+  };
+  pipeline(
+      [&](int a) {
+        return a == 0 ? IntArr{const_cast<int*>(A.cell), A.t_cell} : IntArr{const_cast<int*>(A.id), A.t_id};
+      },
+      A.id ? 2 : 1);
+  // offsets (dims of them), momenta, then the charges when per particle
+  pipeline(
+      [&](int a) {
+        const int d = a < 3 ? a : 2, b = a - dims < 0 ? 0 : (a - dims > 2 ? 2 : a - dims);
+        if (a < dims) return RArr{const_cast<R*>(A.off[d]), A.t_off[d]};
+        if (a - dims < 3) return RArr{const_cast<R*>(A.u[b]), A.t_u[b]};
+        return RArr{const_cast<R*>(A.q), A.t_q};
+      },
+      dims + 3 + (A.q ? 1 : 0));
 }
 
 __global__ void k_fill_int(int* a, long n, int v) {
