@@ -75,6 +75,73 @@ def lds_probe_table(strides=(1, 2, 4, 8, 16, 32, 64, 128)):
     return {op: {str(s): round(lds_rate(op, s), 1) for s in strides} for op in PROBE_OPS}
 
 
+def lds_replay(w, real_bytes, iters=64):
+    """LDS cycles of the push kernel's access patterns (quadratic 3D, 8^3
+    tiles) replayed by the LDS probe (lds_probe_pattern) for the lane layouts
+    that the tile sort produces from this workload's plasma (its first 16 z
+    planes: two layers of tiles, the first 64 tiles), and for the ideal
+    layout (each 32 consecutive lanes on 32 distinct bank residues, one
+    class).  CU cycles per 64-particle batch: the gather (six 27-node
+    stencils) and the current deposit (54 adds of one virtual segment)."""
+    import ctypes as C
+    import torch
+    from paper_1310_0930_amd import build as B
+    from paper_1310_0930_amd.pic import Simulation
+    if w.dims != 3 or w.order != 2 or w.n3[2] < 16:
+        return None
+    lib = C.CDLL(B.PROBE_LIB)
+    RX = 13  # region width: 8-cell tile, one allowance cell and the stencil reach on each side
+
+    def region_cell(lx, ly, lz):
+        return (lx + 2) + RX * ((ly + 2) + RX * (lz + 2))
+
+    w2 = w.with_(n=(w.n3[0], w.n3[1], 16))
+    sim = Simulation.from_workload(w2, real_bytes=real_bytes)
+    sim.load(I.make_plasma(w, slabs=range(16), quiet=False), None, None, with_id=False)
+    sim.sort()
+    st = sim.download()
+    c, o = st["cell"], st["off"]
+    n0, n1 = w.n3[0], w.n3[1]
+    cx, cy, cz = c % n0, (c // n0) % n1, c // (n0 * n1)
+    key = cx // 8 + (n0 // 8) * (cy // 8 + (n1 // 8) * (cz // 8))
+    cls = (o[0] >= 0.5).astype(np.int64) | ((o[1] >= 0.5).astype(np.int64) << 1) | \
+        ((o[2] >= 0.5).astype(np.int64) << 2)
+    lane = region_cell(cx % 8, cy % 8, cz % 8) | (cls << 16)
+    starts = np.searchsorted(key, np.arange(key.max() + 2))
+    pats = []
+    for t in range(min(64, int(key.max()) + 1)):
+        v = lane[starts[t]:starts[t + 1]]
+        pats.append(v[: len(v) // 64 * 64].reshape(-1, 64))
+    rng = np.random.default_rng(1310)
+    lc = np.arange(512)
+    resid = (region_cell(lc % 8, (lc // 8) % 8, lc // 64)) % 32
+    ideal = []
+    for p in range(64):
+        cells = [rng.choice(np.flatnonzero(resid == q)) for h in range(2) for q in range(32)]
+        ideal.append(np.array([region_cell(x % 8, (x // 8) % 8, x // 64) | ((p % 8) << 16) for x in cells]))
+    sink = torch.zeros(1, dtype=torch.int64, device="cuda")
+    stream = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    blocks = 2 * torch.cuda.get_device_properties(0).multi_processor_count
+    modes = {"gather": 4 if real_bytes == 4 else 5, "deposit": 2 if real_bytes == 4 else 3}
+    out = {}
+    for name, pat in (("as_sorted", np.concatenate(pats)), ("ideal", np.stack(ideal))):
+        dev = torch.from_numpy(pat.astype(np.int32).reshape(-1)).cuda()
+        row = {}
+        for what, m in modes.items():
+            ms, best = C.c_float(), float("inf")
+            for _ in range(3):
+                rc = lib.lds_probe_pattern(m, C.c_void_p(dev.data_ptr()), pat.shape[0], iters, blocks,
+                                           C.c_void_p(sink.data_ptr()), stream, C.byref(ms))
+                if rc != 0:
+                    raise RuntimeError(f"lds_probe_pattern({m}) failed: {rc}")
+                best = min(best, ms.value)
+            waves = blocks * 16  # 1024-thread workgroups
+            row[what] = round(best * 1e-3 * CLOCK_HZ / (waves * iters / CUS), 1)
+        out[name] = row
+    out["unit"] = "CU cycles per 64-particle batch"
+    return out
+
+
 def lds_atomics(w, np_, push_ms, real_bytes):
     """LDS atomic throughput of the push/deposit tile kernel against the
     conflict-free rate of the same instruction, measured in this run by the
@@ -110,6 +177,35 @@ def traffic_from_profile(workload, real):
     if rec.get("kernel_hash") != kernel_hash():
         return None
     return rec.get("traffic_bytes")
+
+
+# gfx950: 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz issue 39.3 T lane-instructions
+# of VALU per second without packed FP32 (a wave64 instruction occupies a
+# SIMD for 4 cycles); the LDS of each CU serves one access stream.
+CUS, CLOCK_HZ = 256, 2.4e9
+VALU_PEAK = CUS * 4 * 16 * CLOCK_HZ
+
+
+def ceilings(workload, real, push_ms):
+    """VALU issue and LDS activity of the push/deposit launch: instruction and
+    cycle counts per launch from the committed rocprofv3 SQ counter summary
+    (None when it is absent or the kernel changed since) over the launch's
+    time measured in this run."""
+    path = os.path.join(ROOT, "profiles", f"push_deposit_{workload}_{real}_sq.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("kernel_hash") != kernel_hash():
+        return None
+    t = push_ms * 1e-3
+    valu = rec["valu_insts"] * 64 / t
+    return {"valu_issue": {"achieved": round(valu / 1e12, 2), "peak": round(VALU_PEAK / 1e12, 2),
+                           "unit": "T lane-instructions/s", "frac": round(valu / VALU_PEAK, 4),
+                           "per_64_particles": round(rec["valu_insts"] / rec["batches"], 1)},
+            "lds_active": {"frac": round(rec["lds_active_cycles"] / (CUS * CLOCK_HZ * t), 4),
+                           "conflict_share": round(rec["lds_conflict_cycles"] / rec["lds_active_cycles"], 4),
+                           "cycles_per_64_particles": round(rec["lds_active_cycles"] / rec["batches"], 1)},
+            "source": rec["source"]}
 
 
 _INPUTS = {}
@@ -518,8 +614,15 @@ def summarize_sq(d, log):
             print(f"    {k:22s} {np.mean(v):16.0f} {np.mean(v) / nb:10.1f}")
         if a.get("SQ_LDS_IDX_ACTIVE"):
             print(f"    bank-conflict cycles / LDS-active cycles {sum(a['SQ_LDS_BANK_CONFLICT']) / sum(a['SQ_LDS_IDX_ACTIVE']):.3f}")
-        if a.get("SQ_INSTS_VALU") and a.get("SQ_BUSY_CYCLES"):
-            pass
+        if w in nps and all(a.get(k) for k in ("SQ_INSTS_VALU", "SQ_INSTS_LDS", "SQ_LDS_IDX_ACTIVE")):
+            real = "f64" if "double" in n else "f32"
+            json.dump({"kernel": "k_push_tile", "workload": w, "real": real, "kernel_hash": kernel_hash(),
+                       "batches": int(nb), "valu_insts": float(np.mean(a["SQ_INSTS_VALU"])),
+                       "lds_insts": float(np.mean(a["SQ_INSTS_LDS"])),
+                       "lds_active_cycles": float(np.mean(a["SQ_LDS_IDX_ACTIVE"])),
+                       "lds_conflict_cycles": float(np.mean(a.get("SQ_LDS_BANK_CONFLICT", [0.0]))),
+                       "source": "profiles/push_deposit_sq_counters_" + "_".join(sorted(nps)) + ".txt"},
+                      open(os.path.join(ROOT, "profiles", f"push_deposit_{w}_{real}_sq.json"), "w"), indent=1)
 
 
 def summarize_probe(d, strides=(1, 2, 4, 8, 16, 32, 64, 128), reps=3):
@@ -571,6 +674,8 @@ def main():
     ap.add_argument("--share-steps", type=int, default=10)
     ap.add_argument("--lds-probe", action="store_true",
                     help="also report the LDS probe's rates for every access kind and lane stride")
+    ap.add_argument("--lds-replay", action="store_true",
+                    help="also replay the push kernel's LDS access patterns for the sorted lane layout")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 1 GiB device-to-device copy (for scaling the "
                          "rocprofv3 FETCH_SIZE/WRITE_SIZE counters)")
@@ -626,6 +731,7 @@ def main():
         "rho_deposit_fp64_ms": {k: round(v, 4) for k, v in r32["rho_ms"].items()},
         "roofline": roof(r32, 4, "f32"),
         "lds_atomics": lds_atomics(w, r32["np"], r32["push_ms_mean"], 4),
+        "ceilings": ceilings(w.name, "f32", r32["push_ms_mean"]),
         "slowpath_pushes": r32["slowpath"], "device_flags": r32["flags"],
     }
     if r64:
@@ -634,6 +740,7 @@ def main():
                        "push_deposit_pushes_per_s": r64["np"] / (r64["push_ms_mean"] * 1e-3),
                        "roofline": roof(r64, 8, "f64"),
                        "lds_atomics": lds_atomics(w, r64["np"], r64["push_ms_mean"], 8),
+                       "ceilings": ceilings(w.name, "f64", r64["push_ms_mean"]),
                        "device_flags": r64["flags"]}
     if a.share_workload != "none" and a.share_workload != w.name:
         ws_ = I.WORKLOADS[a.share_workload]
@@ -657,6 +764,7 @@ def main():
                                  "frac": round(ab / (r["push_ms_mean"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                                  "traffic": traffic_from_profile(ws_.name, real),
                                  "alg_bytes_per_launch": ab},
+                    "ceilings": ceilings(ws_.name, real, r["push_ms_mean"]),
                     "slowpath_pushes": r["slowpath"], "device_flags": r["flags"]}
         rec["f32"] = share(s32, 4, "f32")
         if s64:
@@ -664,6 +772,8 @@ def main():
         out["one_gpu_share"] = rec
     if a.lds_probe:
         out["lds_probe"] = {"unit": "G lane-ops/s", "rates_by_stride": lds_probe_table()}
+    if a.lds_replay:
+        out["lds_replay"] = {"f32": lds_replay(w, 4), "f64": None if a.no_fp64 else lds_replay(w, 8)}
     if a.window > 0:
         out["window_shift"] = {"f32": run_window(w, 4, a.window, log)}
         if not a.no_fp64:

@@ -32,8 +32,8 @@ struct SortParams {
   int ntiles;
   int dims;
   FastDiv dn0, dn1;
-  // row and plane strides (elements) of the push kernel's LDS current
-  // region, whose element indices decide the lanes' banks
+  // row and plane strides (elements) of the push kernel's LDS region whose
+  // element indices decide the lanes' banks (region_strides_t)
   int rs1, rs2;
 };
 
@@ -284,13 +284,12 @@ struct PVal {
 // banks and serves a wavefront's 4-byte accesses 32 lanes per cycle and its
 // 8-byte accesses (the current tile's atomics, the double-precision field
 // reads) 16 lanes per cycle, two banks each.  Lanes in one such group go
-// through without conflict when their cells' element indices in the current
-// region differ modulo the group size; 32 consecutive distinct residues
+// through without conflict when their cells' element indices in the region
+// differ modulo the group size; 32 consecutive distinct residues
 // modulo 32 are also 16 distinct residues modulo 16 in each half, so the
 // residue is taken modulo 32 in both precisions (replayed access patterns:
 // modulo 16 costs the double-precision gather and deposit 18 % more LDS
-// cycles).  The field and current regions share their strides at the
-// benchmark orders.  One workgroup lists the tile's cells by residue:
+// cycles).  One workgroup lists the tile's cells by residue:
 // order[0 .. ncells) = cells sorted by (residue, cell),
 // order[TILE_CELLS_MAX + r] = first entry of residue r (r <= RES).
 constexpr int ORDER_NT = 512;
@@ -561,11 +560,17 @@ __global__ void k_fill_int(int* a, long n, int v) {
     a[i] = v;
 }
 
+// The region whose banks the placement balances: the field region in single
+// precision (the gather's 6 (n+1)^D four-byte reads outweigh the deposit's
+// 8-byte adds), the current region in double (its double adds take twice the
+// LDS cycles of the 64-bit integer adds); the two share their strides at
+// even orders.
 template <int DIMS, int ORDER, typename R>
 static void region_strides_t(SortParams& S) {
   using G = Geo<DIMS, ORDER, R>;
-  S.rs1 = G::jx;
-  S.rs2 = DIMS == 3 ? G::jx * G::jx : 0;
+  constexpr int rx = sizeof(R) == 4 ? G::ex : G::jx;
+  S.rs1 = rx;
+  S.rs2 = DIMS == 3 ? rx * rx : 0;
 }
 
 template <typename R>

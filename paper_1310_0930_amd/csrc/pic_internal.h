@@ -61,11 +61,15 @@ struct Geo {
   static constexpr size_t lds_bytes = sizeof(R) * 6 * (size_t)e_vol + sizeof(double) * 3 * (size_t)j_vol;
   // threads per workgroup: in 3D one workgroup fills a CU's LDS, so it
   // brings all the wavefronts: 16 (4 per SIMD, <= 128 VGPRs) in FP32 up to
-  // cubic order, 8 for FP64 and quartic, whose gather and deposit need more
-  // registers; 2D tiles are small and several workgroups share a CU, with
-  // 8 wavefronts each so that a workgroup's batches drain its tile sooner
-  // (a 512 x 256 mesh has only 512 tiles of 16 x 16 for 256 CUs)
-  static constexpr int NT = DIMS == 2 ? 512 : (sizeof(R) == 4 && ORDER <= 3 ? 1024 : 512);
+  // cubic order; 12 (<= 168 VGPRs) for FP64 up to quadratic order and FP32
+  // quartic, whose gather and deposit need more registers (FP64 quadratic
+  // 15 % faster than with 8); 8 for cubic and quartic FP64, which would
+  // spill at 168; 2D tiles are small and several workgroups share a CU,
+  // with 8 wavefronts each so that a workgroup's batches drain its tile
+  // sooner (a 512 x 256 mesh has only 512 tiles of 16 x 16 for 256 CUs)
+  static constexpr int NT = DIMS == 2 ? 512
+                            : sizeof(R) == 4 ? (ORDER <= 3 ? 1024 : 768)
+                                             : (ORDER <= 2 ? 768 : 512);
 };
 
 // Unsigned division by a runtime divisor through a precomputed multiplier

@@ -318,18 +318,21 @@ def test_fdtd_eigenmode_3d_oblique_fp64():
 
 # ---------------------------------------------------------------- edge cases
 def _tile_geometry(dims, order, rb):
-    """Tile sizes and the row/plane strides of the push kernel's LDS current
-    region for a configuration (the tile-kernel geometry)."""
+    """Tile sizes and the row/plane strides of the push kernel's LDS region
+    whose banks the sort balances: the field region in single precision,
+    the current region in double (the tile-kernel geometry)."""
     wide = order == 4 or (rb == 8 and order == 3)
     if dims == 2:
         T, TZ, A = 16, 1, 2
     else:
         T = 4 if (order == 4 and rb == 8) else 8
         TZ, A = (4 if wide else T), 1
-    d_lo = -2 if order >= 3 else -1
-    d_hi = 3 if order >= 3 else 2
-    jx = T + 2 * A + d_hi - d_lo
-    return T, TZ, jx, (jx * jx if dims == 3 else 0)
+    if rb == 4:  # field region: gather reach
+        lo, hi = (-2 if order >= 3 else -1), (1 if order == 1 else 3 if order == 4 else 2)
+    else:  # current region: deposit reach
+        lo, hi = (-2 if order >= 3 else -1), (3 if order >= 3 else 2)
+    rx = T + 2 * A + hi - lo
+    return T, TZ, rx, (rx * rx if dims == 3 else 0)
 
 
 def _check_sorted(w, rb, pl, st):
@@ -342,7 +345,7 @@ def _check_sorted(w, rb, pl, st):
     np.testing.assert_array_equal(st["u"], pl.u[:, ids].astype(np.float64))
     D = w.dims
     n0, n1, _ = w.n3
-    T, TZ, jx, plane = _tile_geometry(D, w.order, rb)
+    T, TZ, rx, plane = _tile_geometry(D, w.order, rb)
     c = st["cell"]
     cx, cy, cz = c % n0, (c // n0) % n1, c // (n0 * n1)
     nt0, nt1 = -(-n0 // T), -(-n1 // T)
@@ -350,8 +353,9 @@ def _check_sorted(w, rb, pl, st):
     assert np.all(np.diff(key) >= 0)
     # inside a tile the particles come class by class (class bit d: offset
     # along d >= 1/2); within a class they are ranked by (k, r): r is the
-    # residue modulo 32 of the cell's element index in the current region
-    # (32 banks), k the number of the class's particles with the same
+    # residue modulo 32 of the cell's element index in the field region
+    # (single precision) or the current region (double) (32 banks), k the
+    # number of the class's particles with the same
     # residue before it, cells taken in cell order.  Particles of one cell are interchangeable, so the cell
     # sequence of every class is unique.
     o = st["off"]
@@ -359,7 +363,7 @@ def _check_sorted(w, rb, pl, st):
     lx, ly, lz = cx % T, cy % T, cz % TZ
     lcell = lx + T * (ly + T * lz)
     nres = 32
-    resid = (lx + jx * ly + plane * lz) % nres
+    resid = (lx + rx * ly + plane * lz) % nres
     big = 0
     for t in np.unique(key):
         m = key == t
