@@ -24,7 +24,7 @@
 namespace pic {
 
 // ------------------------------------------------------------------ kernels
-// Per-wavefront queue of the particles whose path crosses a stencil-switch
+// Workgroup queue of the particles whose path crosses a stencil-switch
 // plane.  A path that stays in one piece of the shape along every axis is a
 // single virtual segment whose ends are the particle's old and new offsets
 // in that piece's frame (nearly every particle of a thermal plasma); a
@@ -33,18 +33,22 @@ namespace pic {
 // crossing in almost every 64-lane wavefront: splitting in place would run
 // the split logic and the extra segments' deposit for the whole wavefront
 // each time.  Instead the main loop deposits only single-segment paths, and
-// crossing paths are queued (structure of arrays in LDS) and deposited 64 at
-// a time, each lane splitting its own path.  Used where the queue still fits
-// next to the tile's field and current regions.
+// crossing paths go to a queue (structure of arrays in LDS) shared by the
+// workgroup's wavefronts, which is split and deposited after the tile's
+// batches in whole 64-lane rounds, each lane splitting its own path (with
+// per-wavefront queues a wavefront collected only about nine paths per tile
+// and drained them in a mostly idle round).  Paths beyond the queue's
+// capacity are split in place.  Used where the queue still fits next to the
+// tile's field and current regions.
 template <int DIMS, int ORDER, typename R>
 struct CrossQueue {
   using G = Geo<DIMS, ORDER, R>;
-  static constexpr int CAP = 96;  // records per wavefront
   static constexpr int NW = G::NT / 64;
   static constexpr int NV = 2 * DIMS + 2;  // o0[D], o1[D], q, q v_z
-  static constexpr size_t bytes = (size_t)NW * CAP * (sizeof(int) + NV * sizeof(R));
+  static constexpr int CAP = 96 * NW;      // records per workgroup
+  static constexpr size_t bytes = (size_t)CAP * (sizeof(int) + NV * sizeof(R));
   static constexpr bool on = G::lds_bytes + bytes + 64 <= 160 * 1024;
-  static constexpr int LEN = on ? NW * CAP : 1;
+  static constexpr int LEN = on ? CAP : 1;
 };
 
 // A queued path: its old cell in the current region and its cell shifts,
@@ -145,6 +149,7 @@ __global__ void __launch_bounds__((Geo<DIMS, ORDER, R>::NT)) k_push_tile(
   // slot i&1, which nobody reads until the next tile.
   __shared__ int s_q[2][3];
   __shared__ int s_batch;  // next batch of the current tile
+  __shared__ int s_qn;     // paths in the crossing queue
 
   const int open0 = P.bc[0] == PIC_BC_OPEN, open1 = P.bc[1] == PIC_BC_OPEN;
   const int open2 = DIMS == 3 && P.bc[2] == PIC_BC_OPEN;
@@ -190,6 +195,7 @@ __global__ void __launch_bounds__((Geo<DIMS, ORDER, R>::NT)) k_push_tile(
     const int nend = __builtin_amdgcn_readfirstlane(s_q[nslot][2]);
     if (threadIdx.x == 0) {
       s_batch = 0;
+      s_qn = 0;
       if (next >= 0) claim = claim_issue(flg, xk);  // for tile i+2
     }
 
@@ -239,29 +245,31 @@ __global__ void __launch_bounds__((Geo<DIMS, ORDER, R>::NT)) k_push_tile(
       s_q[it & 1][2] = e;
     }
     const int lane = threadIdx.x & 63;
-    const int qb = (threadIdx.x >> 6) * Q::CAP;  // this wavefront's queue
-    int qn = 0;                                  // queued paths (wavefront-uniform)
-    // One whole-wavefront round over the last `cnt` queued paths: every lane
-    // splits its path and deposits all of its segments.
-    auto cross_round = [&](int cnt) {
-      __builtin_amdgcn_wave_barrier();
-      if (lane < cnt) {
-        const int r = qb + qn - cnt + lane;
-        int shq[3];
-        const int pb = unpack_path(q_path[r], shq);
-        R a0[3] = {R(0), R(0), R(0)}, a1[3] = {R(0), R(0), R(0)};
+    // The crossing queue, whole 64-path rounds dealt round-robin to the
+    // wavefronts; every lane splits its path and deposits all of its
+    // segments.  In single precision the queue is drained after the barrier
+    // that ends the tile's batches, so that the next tile's field loads stay
+    // in flight meanwhile (and not at all when it is empty); the double
+    // forms drain it before issuing those loads, whose registers would
+    // otherwise spill.
+    constexpr bool drain_late = sizeof(R) == 4;
+    auto drain = [&](int total) {
+      for (int r0 = (threadIdx.x >> 6) * 64; r0 < total; r0 += G::NT) {
+        const int r = r0 + lane;
+        if (r < total) {
+          int shq[3];
+          const int pb = unpack_path(q_path[r], shq);
+          R a0[3] = {R(0), R(0), R(0)}, a1[3] = {R(0), R(0), R(0)};
 #pragma unroll
-        for (int d = 0; d < DIMS; ++d) {
-          a0[d] = q_val[d][r];
-          a1[d] = q_val[DIMS + d][r];
+          for (int d = 0; d < DIMS; ++d) {
+            a0[d] = q_val[d][r];
+            a1[d] = q_val[DIMS + d][r];
+          }
+          deposit_path_lds<DIMS, ORDER, R>(s_j, pb, jf, a0, shq, a1, q_val[2 * DIMS][r],
+                                           q_val[2 * DIMS + 1][r]);
         }
-        deposit_path_lds<DIMS, ORDER, R>(s_j, pb, jf, a0, shq, a1, q_val[2 * DIMS][r],
-                                         q_val[2 * DIMS + 1][r]);
       }
-      __builtin_amdgcn_wave_barrier();
-      qn -= cnt;
     };
-
     // Wavefronts take batches of 64 consecutive particles from a counter in
     // LDS, so that the wavefronts the SIMD arbiter serves first take more
     // and all finish together.  The loop is uniform per wavefront (lanes
@@ -340,10 +348,10 @@ __global__ void __launch_bounds__((Geo<DIMS, ORDER, R>::NT)) k_push_tile(
       const unsigned long long cm = __ballot(cross);
       if (cm == 0ull) continue;
       if constexpr (Q::on) {
-        const int nc = (int)__popcll(cm);
-        if (qn + nc > Q::CAP) cross_round(qn < 64 ? qn : 64);
-        const int pos = qb + qn + (int)__popcll(cm & ((1ull << lane) - 1ull));
-        if (cross) {
+        int q0 = 0;
+        if (lane == 0) q0 = atomicAdd(&s_qn, (int)__popcll(cm));
+        const int pos = __builtin_amdgcn_readfirstlane(q0) + (int)__popcll(cm & ((1ull << lane) - 1ull));
+        if (cross && pos < Q::LEN) {
           q_path[pos] = pack_path(pbase, sh);
 #pragma unroll
           for (int d = 0; d < DIMS; ++d) {
@@ -352,14 +360,17 @@ __global__ void __launch_bounds__((Geo<DIMS, ORDER, R>::NT)) k_push_tile(
           }
           q_val[2 * DIMS][pos] = s.q;
           q_val[2 * DIMS + 1][pos] = fz;
+        } else if (cross) {  // queue full: split in place
+          deposit_path_lds<DIMS, ORDER, R>(s_j, pbase, jf, s.o, sh, o1, s.q, fz);
         }
-        qn += nc;
-        if (qn >= 64) cross_round(64);
       } else {  // no room for a queue: split in place
         if (cross) deposit_path_lds<DIMS, ORDER, R>(s_j, pbase, jf, s.o, sh, o1, s.q, fz);
       }
     }
-    if (Q::on && qn > 0) cross_round(qn);  // drain the queue
+    if constexpr (Q::on && !drain_late) {
+      __syncthreads();
+      drain(min(s_qn, Q::LEN));
+    }
     // (the opaque copy keeps the compiler from forming the next tile's
     // addresses before the particle loop, where registers are scarce)
     int nt = next;
@@ -375,6 +386,13 @@ __global__ void __launch_bounds__((Geo<DIMS, ORDER, R>::NT)) k_push_tile(
         for (int c = 0; c < 6; ++c) stage[k][c] = R(0);
     }
     __syncthreads();
+    if constexpr (Q::on && drain_late) {
+      const int total = min(s_qn, Q::LEN);
+      if (total > 0) {
+        drain(total);
+        __syncthreads();
+      }
+    }
 
     // flush the LDS current tile (its halo overlaps the neighbouring
     // tiles') and clear it for the next tile
