@@ -295,6 +295,7 @@ struct PVal {
 constexpr int ORDER_NT = 512;
 constexpr int TILE_CELLS_MAX = 512;
 constexpr int RES = 32;
+static_assert(RES <= 32, "residue masks are 32-bit words");
 __device__ __forceinline__ int cell_residue(const SortParams& S, int lc) {
   const int lx = lc % S.T[0], ly = (lc / S.T[0]) % S.T[1], lz = lc / (S.T[0] * S.T[1]);
   return (lx + S.rs1 * ly + S.rs2 * lz) % RES;
@@ -353,8 +354,16 @@ __global__ void __launch_bounds__(PLACE_NT) k_sort_place(SortArrays<R> A, SortPa
   __shared__ __align__(16) unsigned char pool[POOL];
   int* const cnt = (int*)pool;                   // particles per (class, cell)
   int* const kb = cnt + NC * TILE_CELLS_MAX;     // k of the first of them
-  __shared__ int cntr[NC][RES];                   // particles per (class, residue)
+  // particles per (class, residue), rows padded so that the lanes of one
+  // wavefront reading one residue of different classes hit different banks
+  __shared__ int cntr[NC][RES + 1];
+  __shared__ int ctot[NC];                        // particles per class
   __shared__ int cls0[NC + 1];                    // first slot of each class
+  // per (class, level k < KT): slots of the levels below k, and the
+  // residues that reach level k (bit mask)
+  constexpr int KT = 64;
+  __shared__ int lvl0[NC][KT];
+  __shared__ unsigned lvlm[NC][KT];
   __shared__ int ord[TILE_CELLS_MAX + RES + 1];
   __shared__ unsigned char res[TILE_CELLS_MAX];
   __shared__ int src[PLACE_SRC_MAX];  // source of each slot of the tile
@@ -424,15 +433,34 @@ __global__ void __launch_bounds__(PLACE_NT) k_sort_place(SortArrays<R> A, SortPa
       k += cnt[key];
     }
     cntr[cls][r] = k;
+    // class total: a class is RES = 32 consecutive lanes of one wavefront
+    int t = k;
+#pragma unroll
+    for (int m = RES / 2; m >= 1; m >>= 1) t += __shfl_xor(t, m, RES);
+    if (r == 0) ctot[cls] = t;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
     int acc = beg;
     for (int c = 0; c < ncls; ++c) {
       cls0[c] = acc;
-      for (int r = 0; r < RES; ++r) acc += cntr[c][r];
+      acc += ctot[c];
     }
     cls0[ncls] = acc;
+  }
+  // per (class, level): slots of the levels below and the residues present
+  for (int t = threadIdx.x; t < ncls * KT; t += PLACE_NT) {
+    const int cls = t / KT, k = t % KT;
+    int below = 0;
+    unsigned m = 0u;
+#pragma unroll
+    for (int q = 0; q < RES; ++q) {
+      const int c = cntr[cls][q];
+      below += min(c, k);
+      m |= (c > k ? 1u : 0u) << q;
+    }
+    lvl0[cls][k] = below;
+    lvlm[cls][k] = m;
   }
   __syncthreads();
   const int n = end - beg;
@@ -443,11 +471,13 @@ __global__ void __launch_bounds__(PLACE_NT) k_sort_place(SortArrays<R> A, SortPa
   // (gathered loads from the copy straight out of memory had each touched a
   // cache line per lane); a larger tile stores directly.
   //
-  // Slot of a particle: rank of (k, r) in the class: every residue with more than k particles
-  // fills levels 0..k, those below r also level k
+  // Slot of a particle: rank of (k, r) in the class: every residue with more
+  // than k particles fills levels 0..k, those below r also level k
   auto slot = [&](int v) {
     const int key = v & 4095, cls = key / TILE_CELLS_MAX, lc = key % TILE_CELLS_MAX;
     const int k = kb[key] + (v >> 12), r = res[lc];
+    if (k < KT)  // levels below k, then the residues below r that reach level k
+      return cls0[cls] + lvl0[cls][k] + (int)__popc(lvlm[cls][k] & ((1u << r) - 1u));
     int pos = 0;
 #pragma unroll
     for (int q = 0; q < RES; ++q) {
