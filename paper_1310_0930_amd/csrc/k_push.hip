@@ -44,11 +44,21 @@ template <int DIMS, int ORDER, typename R>
 struct CrossQueue {
   using G = Geo<DIMS, ORDER, R>;
   static constexpr int NW = G::NT / 64;
-  static constexpr int NV = 2 * DIMS + 2;  // o0[D], o1[D], q, q v_z
-  static constexpr int CAP = 96 * NW;      // records per workgroup
-  static constexpr size_t bytes = (size_t)CAP * (sizeof(int) + NV * sizeof(R));
-  static constexpr bool on = G::lds_bytes + bytes + 64 <= 160 * 1024;
+  static constexpr size_t room = 160 * 1024 - G::lds_bytes - 64;  // LDS left by the regions
+  // full records: cell word, o0[D], o1[D], q, q v_z
+  static constexpr int NV = DIMS + 2;  // the values besides o0
+  static constexpr size_t full_rec = sizeof(int) + (DIMS + NV) * sizeof(R);
+  // compact records (3D): cell word, particle index, o0[3]; the drain reads
+  // o1 and q back from the particle arrays, where the main loop stored them
+  // (the 3D current has no q v_z term)
+  static constexpr size_t compact_rec = 2 * sizeof(int) + DIMS * sizeof(R);
+  static constexpr int full_cap = 96 * NW;
+  static constexpr bool compact = DIMS == 3 && full_cap * full_rec > room;
+  static constexpr int CAP = compact ? (int)(room / compact_rec) : full_cap;
+  static constexpr bool on = CAP >= 64;
   static constexpr int LEN = on ? CAP : 1;
+  static constexpr int LENV = on && !compact ? CAP : 1;  // full records only
+  static constexpr int LENI = on && compact ? CAP : 1;   // compact records only
 };
 
 // A queued path: its old cell in the current region and its cell shifts,
@@ -143,7 +153,9 @@ __global__ void __launch_bounds__((Geo<DIMS, ORDER, R>::NT)) k_push_tile(
   __shared__ R s_eb[6 * G::e_vol];
   __shared__ double s_j[3 * G::j_vol];
   __shared__ int q_path[Q::LEN];
-  __shared__ R q_val[Q::NV][Q::LEN];
+  __shared__ R q_o0[DIMS][Q::LEN];  // the path's old offsets
+  __shared__ R q_val[Q::NV][Q::LENV];  // full records: o1, q, q v_z
+  __shared__ int q_idx[Q::LENI];    // compact records: the particle
   // Tile ids two deep: while tile i runs, slot (i+1)&1 holds tile i+1
   // (tile id, first and end particle) and thread 0 resolves tile i+2 into
   // slot i&1, which nobody reads until the next tile.
@@ -179,7 +191,8 @@ __global__ void __launch_bounds__((Geo<DIMS, ORDER, R>::NT)) k_push_tile(
   stage_load<DIMS, ORDER, R, NR>(P, F, org, stage);
   for (int idx = threadIdx.x; idx < 3 * G::j_vol; idx += G::NT) s_j[idx] = 0.0;
 
-  for (int it = 0;; ++it) {
+  // the staged fields of the next tile from registers into LDS
+  auto write_eb = [&]() {
     const int tid = opaque_tid();
 #pragma unroll
     for (int k = 0; k < NR; ++k) {
@@ -189,6 +202,14 @@ __global__ void __launch_bounds__((Geo<DIMS, ORDER, R>::NT)) k_push_tile(
         for (int c = 0; c < 6; ++c) s_eb[c * G::e_vol + r] = stage[k][c];
       }
     }
+  };
+  // Where the crossing queue is drained before the flush (double forms), the
+  // next tile's fields go to LDS right after the barrier that ends the
+  // batches, which frees their registers for the drain.
+  constexpr bool early_eb = Q::on && sizeof(R) == 8;
+  if constexpr (early_eb) write_eb();  // (the first tile's; the loop writes the next ones at its end)
+  for (int it = 0;; ++it) {
+    if constexpr (!early_eb) write_eb();
     const int nslot = (it + 1) & 1;
     const int next = __builtin_amdgcn_readfirstlane(s_q[nslot][0]);
     const int nbeg = __builtin_amdgcn_readfirstlane(s_q[nslot][1]);
@@ -247,12 +268,13 @@ __global__ void __launch_bounds__((Geo<DIMS, ORDER, R>::NT)) k_push_tile(
     const int lane = threadIdx.x & 63;
     // The crossing queue, whole 64-path rounds dealt round-robin to the
     // wavefronts; every lane splits its path and deposits all of its
-    // segments.  In single precision the queue is drained after the barrier
-    // that ends the tile's batches, so that the next tile's field loads stay
-    // in flight meanwhile (and not at all when it is empty); the double
-    // forms drain it before issuing those loads, whose registers would
-    // otherwise spill.
-    constexpr bool drain_late = sizeof(R) == 4;
+    // segments.  It is drained after the barrier that ends the tile's
+    // batches, with the next tile's field loads in flight meanwhile; in
+    // single precision those loads stay in registers through the drain (and
+    // the drain and its barrier are skipped when the queue is empty), in
+    // double precision they go to LDS first (held through the drain, their
+    // registers would spill).
+    constexpr bool drain_late = !early_eb;
     auto drain = [&](int total) {
       for (int r0 = (threadIdx.x >> 6) * 64; r0 < total; r0 += G::NT) {
         const int r = r0 + lane;
@@ -261,12 +283,19 @@ __global__ void __launch_bounds__((Geo<DIMS, ORDER, R>::NT)) k_push_tile(
           const int pb = unpack_path(q_path[r], shq);
           R a0[3] = {R(0), R(0), R(0)}, a1[3] = {R(0), R(0), R(0)};
 #pragma unroll
-          for (int d = 0; d < DIMS; ++d) {
-            a0[d] = q_val[d][r];
-            a1[d] = q_val[DIMS + d][r];
+          for (int d = 0; d < DIMS; ++d) a0[d] = q_o0[d][r];
+          if constexpr (Q::compact) {
+            const int pp = q_idx[r];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) a1[d] = pa.off[d][pp];
+            deposit_path_lds<DIMS, ORDER, R>(s_j, pb, jf, a0, shq, a1,
+                                             pa.q ? pa.q[pp] : P.q_const, R(0));
+          } else {
+#pragma unroll
+            for (int d = 0; d < DIMS; ++d) a1[d] = q_val[d][r];
+            deposit_path_lds<DIMS, ORDER, R>(s_j, pb, jf, a0, shq, a1, q_val[DIMS][r],
+                                             q_val[DIMS + 1][r]);
           }
-          deposit_path_lds<DIMS, ORDER, R>(s_j, pb, jf, a0, shq, a1, q_val[2 * DIMS][r],
-                                           q_val[2 * DIMS + 1][r]);
         }
       }
     };
@@ -354,22 +383,21 @@ __global__ void __launch_bounds__((Geo<DIMS, ORDER, R>::NT)) k_push_tile(
         if (cross && pos < Q::LEN) {
           q_path[pos] = pack_path(pbase, sh);
 #pragma unroll
-          for (int d = 0; d < DIMS; ++d) {
-            q_val[d][pos] = s.o[d];
-            q_val[DIMS + d][pos] = o1[d];
+          for (int d = 0; d < DIMS; ++d) q_o0[d][pos] = s.o[d];
+          if constexpr (Q::compact) {
+            q_idx[pos] = p;
+          } else {
+#pragma unroll
+            for (int d = 0; d < DIMS; ++d) q_val[d][pos] = o1[d];
+            q_val[DIMS][pos] = s.q;
+            q_val[DIMS + 1][pos] = fz;
           }
-          q_val[2 * DIMS][pos] = s.q;
-          q_val[2 * DIMS + 1][pos] = fz;
         } else if (cross) {  // queue full: split in place
           deposit_path_lds<DIMS, ORDER, R>(s_j, pbase, jf, s.o, sh, o1, s.q, fz);
         }
       } else {  // no room for a queue: split in place
         if (cross) deposit_path_lds<DIMS, ORDER, R>(s_j, pbase, jf, s.o, sh, o1, s.q, fz);
       }
-    }
-    if constexpr (Q::on && !drain_late) {
-      __syncthreads();
-      drain(min(s_qn, Q::LEN));
     }
     // (the opaque copy keeps the compiler from forming the next tile's
     // addresses before the particle loop, where registers are scarce)
@@ -386,7 +414,11 @@ __global__ void __launch_bounds__((Geo<DIMS, ORDER, R>::NT)) k_push_tile(
         for (int c = 0; c < 6; ++c) stage[k][c] = R(0);
     }
     __syncthreads();
-    if constexpr (Q::on && drain_late) {
+    if constexpr (early_eb) {
+      write_eb();
+      drain(min(s_qn, Q::LEN));
+      __syncthreads();
+    } else if constexpr (Q::on) {
       const int total = min(s_qn, Q::LEN);
       if (total > 0) {
         drain(total);
