@@ -203,10 +203,11 @@ __global__ void __launch_bounds__((Geo<DIMS, ORDER, R>::NT)) k_push_tile(
       }
     }
   };
-  // Where the crossing queue is drained before the flush (double forms), the
-  // next tile's fields go to LDS right after the barrier that ends the
-  // batches, which frees their registers for the drain.
-  constexpr bool early_eb = Q::on && sizeof(R) == 8;
+  // Where there is a crossing queue, the next tile's fields go to LDS right
+  // after the barrier that ends the batches, which frees their registers for
+  // the drain (held through it, they spilled in the double forms' batch
+  // loop; single precision gains 1 %).
+  constexpr bool early_eb = Q::on;
   if constexpr (early_eb) write_eb();  // (the first tile's; the loop writes the next ones at its end)
   for (int it = 0;; ++it) {
     if constexpr (!early_eb) write_eb();
@@ -269,12 +270,7 @@ __global__ void __launch_bounds__((Geo<DIMS, ORDER, R>::NT)) k_push_tile(
     // The crossing queue, whole 64-path rounds dealt round-robin to the
     // wavefronts; every lane splits its path and deposits all of its
     // segments.  It is drained after the barrier that ends the tile's
-    // batches, with the next tile's field loads in flight meanwhile; in
-    // single precision those loads stay in registers through the drain (and
-    // the drain and its barrier are skipped when the queue is empty), in
-    // double precision they go to LDS first (held through the drain, their
-    // registers would spill).
-    constexpr bool drain_late = !early_eb;
+    // batches, once the next tile's fields (loaded meanwhile) are in LDS.
     auto drain = [&](int total) {
       for (int r0 = (threadIdx.x >> 6) * 64; r0 < total; r0 += G::NT) {
         const int r = r0 + lane;
@@ -415,10 +411,9 @@ __global__ void __launch_bounds__((Geo<DIMS, ORDER, R>::NT)) k_push_tile(
     }
     __syncthreads();
     if constexpr (early_eb) {
+      // (the next tile reads s_eb after the barrier at the top of the loop;
+      // the flush needs one more barrier only after a drain)
       write_eb();
-      drain(min(s_qn, Q::LEN));
-      __syncthreads();
-    } else if constexpr (Q::on) {
       const int total = min(s_qn, Q::LEN);
       if (total > 0) {
         drain(total);
