@@ -161,9 +161,14 @@ def lds_atomics(w, np_, push_ms, real_bytes):
 
 
 def kernel_hash():
+    """Hash of the push kernel's sources without comments and blank space
+    (a comment-only edit keeps the committed counter summaries valid)."""
+    import re
     h = hashlib.sha256()
     for f in ("k_push.hip", "k_particle.h", "k_common.h", "pic_internal.h"):
-        h.update(open(os.path.join(ROOT, "paper_1310_0930_amd", "csrc", f), "rb").read())
+        src = open(os.path.join(ROOT, "paper_1310_0930_amd", "csrc", f)).read()
+        src = re.sub(r"//[^\n]*|/\*.*?\*/", "", src, flags=re.S)
+        h.update("".join(src.split()).encode())
     return h.hexdigest()[:16]
 
 

@@ -298,9 +298,9 @@ __global__ void __launch_bounds__((Geo<DIMS, ORDER, R>::NT)) k_push_tile(
     // Wavefronts take batches of 64 consecutive particles from a counter in
     // LDS, so that the wavefronts the SIMD arbiter serves first take more
     // and all finish together.  The loop is uniform per wavefront (lanes
-    // past the end are idle) so that whole-wavefront queue rounds see every
-    // lane.  The next batch is taken, and its particle state loaded, one
-    // iteration ahead.
+    // past the end are idle) so that the queue's ballot sees every lane.
+    // The next batch is taken, and its particle state loaded, one iteration
+    // ahead.
     int p = pbase_of_batch(pbeg, take_batch(&s_batch), lane), pn;
     PState<R> nxt;
     if (p < pend) nxt = load_particle<DIMS, R>(pa, p, P.q_const);
