@@ -143,6 +143,22 @@ def test_parity_relativistic_drift_slow_path(rb):
     _check(compare(w, sim, ref), rb, "hot drift")
 
 
+@pytest.mark.parametrize("rb", [8, 4])
+def test_parity_crossing_queue_overflow(rb):
+    """A dense warm plasma (16 ppc, u_th = 0.4: 8192 particles per 8^3 tile,
+    about a fifth of them crossing a stencil-switch plane each step, moves
+    well below half a cell) overflows the workgroup's crossing queue (1536
+    full records in FP32, 174 compact ones in FP64): the paths beyond it are
+    split in place.  Every path must land as the oracle's does."""
+    w = I.Workload("w3d_dense", 3, (24, 16, 16), (0.2, 0.2, 0.2), 2, 16, 0.4, 4,
+                   seed=I.SEED_BASE + 55)
+    sim, ref = _run(w, rb, w.steps, sort_every=2)
+    flags, nslow = sim.read_flags()
+    say("crossing overflow", rb, "slow path pushes", nslow, "flags", flags)
+    assert flags == 0
+    _check(compare(w, sim, ref), rb, "crossing queue overflow")
+
+
 # ---------------------------------------------------------------- full size
 @pytest.mark.parametrize("rb", [4, 8])
 def test_parity_full_128_quadratic_two_steps(rb):
