@@ -55,7 +55,7 @@ struct CrossQueue {
   static constexpr int full_cap = 96 * NW;
   static constexpr bool compact = DIMS == 3 && full_cap * full_rec > room;
   static constexpr int CAP = compact ? (int)(room / compact_rec) : full_cap;
-  static constexpr bool on = CAP >= 64;
+  static constexpr bool on = compact ? CAP >= 64 : full_cap * full_rec <= room;
   static constexpr int LEN = on ? CAP : 1;
   static constexpr int LENV = on && !compact ? CAP : 1;  // full records only
   static constexpr int LENI = on && compact ? CAP : 1;   // compact records only
