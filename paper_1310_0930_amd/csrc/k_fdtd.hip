@@ -169,7 +169,9 @@ __global__ void k_advance_e(FdParams P, MurPlanes M, R* __restrict__ E0, R* __re
 // per (i, j) column of FD_KC consecutive z planes: the column's index
 // arithmetic and wraps are formed once, and the z neighbour of one plane is
 // the next plane's centre sample, kept in registers.  Consecutive threads
-// take consecutive x, so every load and store stays coalesced.
+// take consecutive x, so every load and store stays coalesced, and the x
+// neighbour is the adjacent lane's own sample, passed across the wavefront;
+// only a lane at the wavefront's or the row's end loads it.
 constexpr int FD_KC = 4;
 
 __device__ __forceinline__ int column_start(const FdParams& P, int t, int& i, int& j, int& k0) {
@@ -194,13 +196,20 @@ __global__ void k_half_b_col(FdParams P, const R* __restrict__ E0, const R* __re
   const int ip = i + 1 < P.n[0] ? 1 : 1 - P.n[0];
   const int jp = j + 1 < P.n[1] ? P.n[0] : P.n[0] - plane;
   R exk = E0[idx], eyk = E1[idx];  // E_x, E_y at plane k
+  const int lane = threadIdx.x & 63;
+  const bool own = lane < 63 && i + 1 < P.n[0];  // the x neighbour is the next lane's sample
 #pragma unroll
   for (int kk = 0; kk < FD_KC; ++kk, idx += plane) {
     const int kp = k0 + kk + 1 < P.n[2] ? plane : plane - P.n[2] * plane;
     const R ex1 = E0[idx + kp], ey1 = E1[idx + kp], ez = E2[idx];
+    R ezx = __shfl_down(ez, 1, 64), eyx = __shfl_down(eyk, 1, 64);
+    if (!own) {
+      ezx = E2[idx + ip];
+      eyx = E1[idx + ip];
+    }
     B0[idx] -= hy * (E2[idx + jp] - ez) - hz * (ey1 - eyk);
-    B1[idx] -= hz * (ex1 - exk) - hx * (E2[idx + ip] - ez);
-    B2[idx] -= hx * (E1[idx + ip] - eyk) - hy * (E0[idx + jp] - exk);
+    B1[idx] -= hz * (ex1 - exk) - hx * (ezx - ez);
+    B2[idx] -= hx * (eyx - eyk) - hy * (E0[idx + jp] - exk);
     exk = ex1;
     eyk = ey1;
   }
@@ -222,12 +231,19 @@ __global__ void k_advance_e_col(FdParams P, R* __restrict__ E0, R* __restrict__ 
   const int jm = j > 0 ? -P.n[0] : plane - P.n[0];
   const int km = k0 > 0 ? -plane : (P.n[2] - 1) * plane;
   R bxm = B0[idx + km], bym = B1[idx + km];  // B_x, B_y at plane k - 1
+  const int lane = threadIdx.x & 63;
+  const bool own = lane > 0 && i > 0;  // the -x neighbour is the previous lane's sample
 #pragma unroll
   for (int kk = 0; kk < FD_KC; ++kk, idx += plane) {
     const R bx = B0[idx], by = B1[idx], bz = B2[idx];
+    R bzx = __shfl_up(bz, 1, 64), byx = __shfl_up(by, 1, 64);
+    if (!own) {
+      bzx = B2[idx + im];
+      byx = B1[idx + im];
+    }
     E0[idx] += (gy * (bz - B2[idx + jm]) - gz * (by - bym)) - dt * J0[idx];
-    E1[idx] += (gz * (bx - bxm) - gx * (bz - B2[idx + im])) - dt * J1[idx];
-    E2[idx] += (gx * (by - B1[idx + im]) - gy * (bx - B0[idx + jm])) - dt * J2[idx];
+    E1[idx] += (gz * (bx - bxm) - gx * (bz - bzx)) - dt * J1[idx];
+    E2[idx] += (gx * (by - byx) - gy * (bx - B0[idx + jm])) - dt * J2[idx];
     bxm = bx;
     bym = by;
   }
