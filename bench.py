@@ -225,6 +225,12 @@ def workload_inputs(w):
     return _INPUTS[w.name]
 
 
+def sorts_in(warmup, steps, every):
+    """Sorts inside the timed steps warmup .. warmup + steps - 1 (step k sorts
+    first when k is a multiple of the interval)."""
+    return sum(1 for k in range(warmup, warmup + steps) if k % every == 0)
+
+
 def run_gpu(w, real_bytes, steps, warmup, log):
     import torch
     from paper_1310_0930_amd.pic import Simulation
@@ -271,11 +277,12 @@ def run_gpu(w, real_bytes, steps, warmup, log):
     total_ms = t0.elapsed_time(t1)
     push_ms = [a.elapsed_time(b) for a, b, _ in evs]
     fdtd_ms = [b.elapsed_time(c) for _, b, c in evs]
-    flags, nslow = 0, 0
+    flags, nslow, nreb = 0, 0, 0
     for s in everyone:
         f_, n_ = s.read_flags()
         flags |= f_
         nslow += n_
+        nreb += s.read_push_counts()[0]
     diag = sim.diagnostics()
     # FP64 charge density of the resident particles: tiles of the last sort
     # (LDS) and one thread per particle (no bins)
@@ -293,12 +300,13 @@ def run_gpu(w, real_bytes, steps, warmup, log):
         rho_ms[tag] = e0.elapsed_time(e1) / 3
     log(f"{w.name} real={real_bytes}: {total_ms / steps:.3f} ms/step, push {np.mean(push_ms):.3f} ms, "
         f"fdtd {np.mean(fdtd_ms):.3f} ms, rho {rho_ms['tiles']:.3f} ms (per particle "
-        f"{rho_ms['per_particle']:.3f}), slow={nslow} flags={flags}")
+        f"{rho_ms['per_particle']:.3f}), rebinned={nreb} slow={nslow} flags={flags}")
     return {
         "np": np_total, "ms_per_step": total_ms / steps, "wall_s": wall,
         "push_ms_mean": float(np.mean(push_ms)), "push_ms_median": float(np.median(push_ms)),
         "fdtd_ms_mean": float(np.mean(fdtd_ms)), "rho_ms": rho_ms,
-        "slowpath": int(nslow), "flags": int(flags), "n_alive": int(diag.raw["n_alive"]),
+        "slowpath": int(nslow), "rebinned": int(nreb), "flags": int(flags),
+        "n_alive": int(diag.raw["n_alive"]),
     }
 
 
@@ -590,7 +598,7 @@ def summarize_bytes(dfetch, dwrite, log):
         t = (f * fs + wr * ws_) * 1024
         line = (f"  {w:26s} {n:44s} FETCH {f:12.1f} WRITE {wr:12.1f} KiB "
                 f"({len(v.get('FETCH_SIZE', []))} dispatches)  {t / 1e6:10.1f} MB")
-        if "k_push_tile" in n and w in nps:
+        if "k_push_tile" in n and ", true>" not in n and w in nps:  # the sorted pass
             rb = 8 if "double" in n else 4
             ab = algorithmic_bytes(I.WORKLOADS[w], nps[w], rb)
             line += f"  algorithmic {ab / 1e6:.1f} MB, ratio {t / ab:.3f}"
@@ -608,7 +616,7 @@ def summarize_sq(d, log):
     nps = _rp_particles(_rp_record(log))
     agg = {}
     for _, n, c, w in _rp_counters(d):
-        if "k_push_tile" in n:
+        if "k_push_tile" in n and ", true>" not in n:  # the sorted pass
             a = agg.setdefault((w, _rp_short(n)), {})
             for k, v in c.items():
                 a.setdefault(k, []).append(v)
@@ -676,7 +684,9 @@ def main():
     ap.add_argument("--share-workload", default="w3d_512_quadratic_laser",
                     choices=sorted(I.WORKLOADS) + ["none"],
                     help="second record: the one-GPU share of an LWFA run (FP32 and FP64)")
-    ap.add_argument("--share-steps", type=int, default=10)
+    ap.add_argument("--share-steps", type=int, default=0,
+                    help="timed steps of the share (default: one sort interval of its workload, so "
+                         "that the whole-step rate carries exactly one sort)")
     ap.add_argument("--lds-probe", action="store_true",
                     help="also report the LDS probe's rates for every access kind and lane stride")
     ap.add_argument("--lds-replay", action="store_true",
@@ -729,7 +739,8 @@ def main():
         "config": {"workload": w.name, "dims": w.dims, "grid": list(w.n3), "dx": list(w.dx3),
                    "ppc": w.ppc, "particles": r32["np"], "order": w.order, "u_th": w.u_th,
                    "species": 1 if w.ions is None else 2,
-                   "dt": w.dt, "sort_every": w.sort_every, "boundaries": list(w.bc3),
+                   "dt": w.dt, "sort_every": w.sort_every,
+                   "sorts_timed": sorts_in(a.warmup, a.steps, w.sort_every), "boundaries": list(w.bc3),
                    "parallelism": "single GPU"},
         "push_deposit_pushes_per_s": r32["np"] / (r32["push_ms_mean"] * 1e-3),
         "field_advance_ms": round(r32["fdtd_ms_mean"], 5),
@@ -737,7 +748,8 @@ def main():
         "roofline": roof(r32, 4, "f32"),
         "lds_atomics": lds_atomics(w, r32["np"], r32["push_ms_mean"], 4),
         "ceilings": ceilings(w.name, "f32", r32["push_ms_mean"]),
-        "slowpath_pushes": r32["slowpath"], "device_flags": r32["flags"],
+        "rebinned_pushes": r32["rebinned"], "slowpath_pushes": r32["slowpath"],
+        "device_flags": r32["flags"],
     }
     if r64:
         out["fp64"] = {"value": r64["np"] / (r64["ms_per_step"] * 1e-3),
@@ -749,12 +761,13 @@ def main():
                        "device_flags": r64["flags"]}
     if a.share_workload != "none" and a.share_workload != w.name:
         ws_ = I.WORKLOADS[a.share_workload]
-        k5 = max(1, a.share_steps)
+        k5 = a.share_steps if a.share_steps > 0 else ws_.sort_every
         s32 = run_gpu(ws_, 4, k5, 3, log)
         s64 = None if a.no_fp64 else run_gpu(ws_, 8, k5, 3, log)
         rec = {"workload": ws_.name, "grid": list(ws_.n3), "dx": list(ws_.dx3), "ppc": ws_.ppc,
                "order": ws_.order, "particles": s32["np"], "dt": ws_.dt,
-               "sort_every": ws_.sort_every, "steps": k5, "warmup": 3}
+               "sort_every": ws_.sort_every, "steps": k5, "warmup": 3,
+               "sorts_timed": sorts_in(3, k5, ws_.sort_every)}
 
         def share(r, rb, real):
             ab = algorithmic_bytes(ws_, r["np"], rb)
@@ -770,7 +783,8 @@ def main():
                                  "traffic": traffic_from_profile(ws_.name, real),
                                  "alg_bytes_per_launch": ab},
                     "ceilings": ceilings(ws_.name, real, r["push_ms_mean"]),
-                    "slowpath_pushes": r["slowpath"], "device_flags": r["flags"]}
+                    "rebinned_pushes": r["rebinned"], "slowpath_pushes": r["slowpath"],
+                    "device_flags": r["flags"]}
         rec["f32"] = share(s32, 4, "f32")
         if s64:
             rec["f64"] = share(s64, 8, "f64")

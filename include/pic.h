@@ -83,8 +83,8 @@ typedef struct {
   int32_t bc[3];      /* pic_bc per axis (ignored for z in 2D) */
   int32_t tile[3];    /* cells per tile per axis; 0 selects the default */
   int32_t sort_every; /* pic_step re-sorts every this many steps (>= 1) */
-  int32_t drift;      /* cells a particle may drift out of its tile before it
-                         takes the global-memory path; < 0 selects the default */
+  int32_t drift;      /* cells a particle may drift out of its tile before the
+                         push re-bins it; < 0 selects the default */
   double q_over_m;    /* charge-to-mass ratio of the species, in e/m_e (-1 for
                          electrons, Z m_e/m_i for ions); one context per species */
   double q_const;     /* charge of every particle when pic_particles.q is NULL */
@@ -174,7 +174,14 @@ int pic_sort(pic_ctx* ctx, pic_particles* p, void* ws, void* stream);
  * over all live particles (Sec. 2 loop; Sec. 5.2 steps i-v): reads E^n, B^n
  * at the particles, advances u^{n-1/2} -> u^{n+1/2} and x^n -> x^{n+1} in
  * place, and overwrites f->J with J^{n+1/2}.  Requires a prior pic_sort with
- * the same particle arrays and workspace (PIC_ESTATE otherwise). */
+ * the same particle arrays and workspace (PIC_ESTATE otherwise).  Particles
+ * within `drift` cells of the tile the sort put them in are pushed tile by
+ * tile out of LDS; those that have drifted further are re-binned by the tile
+ * of their current cell and pushed out of LDS in a second tile pass (the
+ * arrays keep their order; only the next pic_sort moves them); a particle
+ * that moves half a cell or more in one step, or whose |q| exceeds the bound
+ * the sort recorded, is pushed in global memory.  The result does not depend
+ * on the path beyond the rounding of the current's accumulation. */
 int pic_push_deposit(pic_ctx* ctx, pic_particles* p, const pic_fields* f, void* ws,
                      void* stream);
 
@@ -297,9 +304,17 @@ int pic_push_deposit_adjoint(pic_ctx* ctx, const pic_particles* state_n, const p
                              pic_fields* lam_f, pic_particles* lam_p, void* ws, void* stream);
 
 /* Read (and optionally clear) the sticky device flags and the slow-path
- * counter (synchronises `stream`).  Returns PIC_EDEVICE if any flag is set. */
+ * counter (synchronises `stream`).  Returns PIC_EDEVICE if any flag is set.
+ * Clearing also clears the re-binned count of pic_read_push_counts. */
 int pic_read_flags(pic_ctx* ctx, void* ws, int clear, uint32_t* flags, int64_t* n_slowpath,
                    void* stream);
+
+/* Pushes since the last clear of the flags in `ws` that left the sorted tile
+ * pass of pic_push_deposit: *n_rebinned handed to the re-binned tile pass,
+ * *n_slowpath done in global memory (either pointer may be NULL).  Host
+ * outputs; synchronises `stream`; PIC_EINVAL for a NULL ctx or ws. */
+int pic_read_push_counts(pic_ctx* ctx, void* ws, int64_t* n_rebinned, int64_t* n_slowpath,
+                         void* stream);
 
 /* Human-readable name of a status code. */
 const char* pic_strerror(int status);

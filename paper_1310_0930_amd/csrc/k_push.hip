@@ -121,6 +121,26 @@ __device__ inline int claim_resolve(unsigned local, const int* __restrict__ star
   return -1;
 }
 
+// Claims of the re-binned pass: one counter over the destination tiles
+// listed by the sorted pass (each holds at least one particle).
+__device__ inline unsigned rb_claim_issue(DevFlags* flg) { return atomicAdd(&flg->rb_next, 1u); }
+__device__ inline int rb_claim_resolve(unsigned v, const DevFlags* flg, const Rebin& rb, int& beg,
+                                       int& end) {
+  if (v >= flg->rb_m) return -1;
+  const int t = rb.nl[v];
+  beg = rb.base[v];
+  end = beg + rb.cnt[t];
+  return t;
+}
+
+// Tile of a cell (the sort's tile numbering).
+template <int DIMS, int ORDER, typename R>
+__device__ __forceinline__ int cell_tile(const KParams<R>& P, const int* c3) {
+  using G = Geo<DIMS, ORDER, R>;
+  const int tz = DIMS == 3 ? c3[2] / G::TZ : 0;
+  return c3[0] / G::T + P.ntile[0] * (c3[1] / G::T + P.ntile[1] * tz);
+}
+
 // The low 48 bits of a fixed-point tile sum, sign-extended (the sum itself).
 __device__ __forceinline__ long long sext48(long long x) {
   return (long long)((unsigned long long)x << 16) >> 16;
@@ -137,17 +157,22 @@ __device__ __forceinline__ int take_batch(int* ctr) {
 }
 
 // Tile kernel: persistent workgroups, each taking tiles until none is left;
-// particles within the drift allowance of the tile run out of LDS.  Any
-// other particle (drifted further, or moving half a cell or more in one
-// step) is left untouched and appended to the deferred list for
+// particles within the drift allowance of the tile run out of LDS.  The
+// sorted pass (RB = false) takes the tiles of the last sort; a particle that
+// has drifted beyond its tile's allowance (or moves half a cell or more in
+// one step, or carries a charge above the sort's bound) is left untouched
+// and appended to the deferred list.  The re-binned pass (RB = true) takes
+// the deferred particles grouped by the tile of their current cell
+// (k_rebin_count, k_rebin_scatter), so that those that drifted run out of
+// LDS too; what it cannot take either is left untouched for
 // k_push_deferred.  The tiles of one workgroup are software-pipelined: a
 // wavefront that has finished its particles issues the loads of the next
 // tile's fields (into registers) while the other wavefronts finish, and
 // the flush of the current tile's current runs while they are in flight.
-template <int DIMS, int ORDER, typename R>
+template <int DIMS, int ORDER, typename R, bool RB>
 __global__ void __launch_bounds__((Geo<DIMS, ORDER, R>::NT)) k_push_tile(
     KParams<R> P, DParts<R> pa, DFields<R> F, const int* __restrict__ starts,
-    int* __restrict__ deferred, DevFlags* flg) {
+    int* __restrict__ deferred, DevFlags* flg, Rebin rb) {
   using G = Geo<DIMS, ORDER, R>;
   using Q = CrossQueue<DIMS, ORDER, R>;
   __shared__ R s_eb[6 * G::e_vol];
@@ -168,13 +193,25 @@ __global__ void __launch_bounds__((Geo<DIMS, ORDER, R>::NT)) k_push_tile(
   const int str1 = P.n[0], str2 = P.n[0] * P.n[1];
   int xk = 0;           // thread 0: ranges used up
   unsigned claim = 0u;  // thread 0: claim in flight
+  auto issue = [&]() -> unsigned {
+    if constexpr (RB)
+      return rb_claim_issue(flg);
+    else
+      return claim_issue(flg, xk);
+  };
+  auto resolve = [&](unsigned c, int& b, int& e) -> int {
+    if constexpr (RB)
+      return rb_claim_resolve(c, flg, rb, b, e);
+    else
+      return claim_resolve(c, starts, flg, P.per_xcd, P.ntiles, xk, b, e);
+  };
   if (threadIdx.x == 0) {
     int b = 0, e = 0;
-    const int t0 = claim_resolve(claim_issue(flg, xk), starts, flg, P.per_xcd, P.ntiles, xk, b, e);
+    const int t0 = resolve(issue(), b, e);
     s_q[0][0] = t0;
     s_q[0][1] = b;
     s_q[0][2] = e;
-    const int t1 = t0 < 0 ? -1 : claim_resolve(claim_issue(flg, xk), starts, flg, P.per_xcd, P.ntiles, xk, b, e);
+    const int t1 = t0 < 0 ? -1 : resolve(issue(), b, e);
     s_q[1][0] = t1;
     s_q[1][1] = b;
     s_q[1][2] = e;
@@ -218,7 +255,7 @@ __global__ void __launch_bounds__((Geo<DIMS, ORDER, R>::NT)) k_push_tile(
     if (threadIdx.x == 0) {
       s_batch = 0;
       s_qn = 0;
-      if (next >= 0) claim = claim_issue(flg, xk);  // for tile i+2
+      if (next >= 0) claim = issue();  // for tile i+2
     }
 
     // Scales of the fixed-point current tile (single form).  A contribution
@@ -261,7 +298,7 @@ __global__ void __launch_bounds__((Geo<DIMS, ORDER, R>::NT)) k_push_tile(
     __syncthreads();
     if (threadIdx.x == 0) {  // tile i+2 (wavefront 0 starts its particles later)
       int t2 = -1, b = 0, e = 0;
-      if (next >= 0) t2 = claim_resolve(claim, starts, flg, P.per_xcd, P.ntiles, xk, b, e);
+      if (next >= 0) t2 = resolve(claim, b, e);
       s_q[it & 1][0] = t2;
       s_q[it & 1][1] = b;
       s_q[it & 1][2] = e;
@@ -301,13 +338,18 @@ __global__ void __launch_bounds__((Geo<DIMS, ORDER, R>::NT)) k_push_tile(
     // past the end are idle) so that the queue's ballot sees every lane.
     // The next batch is taken, and its particle state loaded, one iteration
     // ahead.
+    // (p: position in the tile's range; pi: the particle, through the list
+    // in the re-binned pass)
     int p = pbase_of_batch(pbeg, take_batch(&s_batch), lane), pn;
+    int qn = RB ? (p < pend ? rb.list[p] : 0) : p;
     PState<R> nxt;
-    if (p < pend) nxt = load_particle<DIMS, R>(pa, p, P.q_const);
+    if (p < pend) nxt = load_particle<DIMS, R>(pa, qn, P.q_const);
     for (; p - lane < pend; p = pn) {
+      const int pi = qn;
       PState<R> s = nxt;
       pn = pbase_of_batch(pbeg, take_batch(&s_batch), lane);
-      if (pn < pend) nxt = load_particle<DIMS, R>(pa, pn, P.q_const);
+      qn = RB ? (pn < pend ? rb.list[pn] : 0) : pn;
+      if (pn < pend) nxt = load_particle<DIMS, R>(pa, qn, P.q_const);
       bool valid = p < pend && s.cl >= 0;
       int c3[3] = {0, 0, 0};
       if (valid) valid = decode<DIMS, R>(P, s, c3, flg);
@@ -329,8 +371,11 @@ __global__ void __launch_bounds__((Geo<DIMS, ORDER, R>::NT)) k_push_tile(
       R o1[3] = {R(0), R(0), R(0)}, vz = R(0);
       int sh[3] = {0, 0, 0};
       if (G::fixed && pa.q && !(fabs(s.q) <= qmax && qmax_ok)) fast = false;
-      if (valid && !fast) {  // leave the state as it was; the global-memory kernel redoes it
-        deferred[atomicAdd(&flg->ndefer, 1u)] = p;
+      if (valid && !fast) {  // leave the state as it was; a later pass redoes it
+        if constexpr (RB)
+          rb.defer2[atomicAdd(&flg->ndefer2, 1u)] = pi;
+        else
+          deferred[atomicAdd(&flg->ndefer, 1u)] = pi;
         valid = false;
       }
       if (valid) {
@@ -340,10 +385,13 @@ __global__ void __launch_bounds__((Geo<DIMS, ORDER, R>::NT)) k_push_tile(
         gather<DIMS, ORDER, R>(acc, s.o, Ep, Bp);
         bool small = false;
         if (!push_move<DIMS, R>(P, s, Ep, Bp, sh, o1, vz, small, flg)) {
-          pa.cell[p] = -1;
+          pa.cell[pi] = -1;
           valid = false;
         } else if (!small) {
-          deferred[atomicAdd(&flg->ndefer, 1u)] = p;
+          if constexpr (RB)
+            rb.defer2[atomicAdd(&flg->ndefer2, 1u)] = pi;
+          else
+            deferred[atomicAdd(&flg->ndefer, 1u)] = pi;
           valid = false;
         }
       }
@@ -368,7 +416,7 @@ __global__ void __launch_bounds__((Geo<DIMS, ORDER, R>::NT)) k_push_tile(
         sink.segment(base);
         deposit_segment<DIMS, ORDER, R>(sink, jf, xa, xb, s.q, fz);
       }
-      if (valid) store_particle<DIMS, R>(pa, p, s, o1, new_cell<DIMS, R>(P, c3, sh));
+      if (valid) store_particle<DIMS, R>(pa, pi, s, o1, new_cell<DIMS, R>(P, c3, sh));
       // paths that cross a stencil-switch plane
       const unsigned long long cm = __ballot(cross);
       if (cm == 0ull) continue;
@@ -381,7 +429,7 @@ __global__ void __launch_bounds__((Geo<DIMS, ORDER, R>::NT)) k_push_tile(
 #pragma unroll
           for (int d = 0; d < DIMS; ++d) q_o0[d][pos] = s.o[d];
           if constexpr (Q::compact) {
-            q_idx[pos] = p;
+            q_idx[pos] = pi;
           } else {
 #pragma unroll
             for (int d = 0; d < DIMS; ++d) q_val[d][pos] = o1[d];
@@ -469,14 +517,101 @@ __global__ void __launch_bounds__((Geo<DIMS, ORDER, R>::NT)) k_push_tile(
   }
 }
 
+// Tile of the current cell of deferred particle i (the decomposition of
+// decode()).
+template <int DIMS, int ORDER, typename R>
+__device__ __forceinline__ int deferred_tile(const KParams<R>& P, const int* __restrict__ cell,
+                                             const int* __restrict__ deferred, int i) {
+  const uint32_t cl = (uint32_t)cell[deferred[i]];
+  const uint32_t rest = P.dn0.div(cl);
+  int c3[3] = {(int)cl - (int)rest * P.n[0], (int)rest, 0};
+  if (DIMS == 3) {
+    const uint32_t r2 = P.dn1.div(rest);
+    c3[1] = (int)(rest - r2 * P.n[1]);
+    c3[2] = (int)r2;
+  }
+  return cell_tile<DIMS, ORDER, R>(P, c3);
+}
+
+// Counts the deferred particles of the sorted pass per destination tile
+// (the tile of their current cell), giving each its rank there and listing
+// the destination tiles in order of their first particle; the last
+// workgroup to finish turns the counts into first list positions
+// (exclusive prefix sum in the order of rb.nl).  Every thread fences its
+// own writes before its workgroup counts itself as finished.
+constexpr int RB_NT = 256;
+template <int DIMS, int ORDER, typename R>
+__global__ void __launch_bounds__(RB_NT) k_rebin_count(KParams<R> P, const int* __restrict__ cell,
+                                                       const int* __restrict__ deferred, Rebin rb,
+                                                       DevFlags* flg) {
+  __shared__ int sc[2 * RB_NT];
+  __shared__ int s_last;
+  const int nd = (int)flg->ndefer;
+  for (int i = blockIdx.x * RB_NT + threadIdx.x; i < nd; i += gridDim.x * RB_NT) {
+    const int t = deferred_tile<DIMS, ORDER, R>(P, cell, deferred, i);
+    const int r = atomicAdd(&rb.cnt[t], 1);
+    rb.rank[i] = r;
+    if (r == 0) {
+      const unsigned v = atomicAdd(&flg->rb_m, 1u);
+      rb.nl[v] = t;
+      rb.tv[t] = (int)v;
+    }
+  }
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) s_last = atomicAdd(&flg->rb_done, 1u) == gridDim.x - 1 ? 1 : 0;
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  const int m = (int)__hip_atomic_load(&flg->rb_m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const int tid = threadIdx.x;
+  int run = 0;
+  for (int c0 = 0; c0 < m; c0 += RB_NT) {
+    const int v = c0 + tid;
+    int n = 0;
+    if (v < m) {
+      const int t = __hip_atomic_load(&rb.nl[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      n = __hip_atomic_load(&rb.cnt[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    sc[tid] = n;
+    __syncthreads();
+    int pin = 0;
+    for (int o = 1; o < RB_NT; o <<= 1) {
+      int x = sc[pin * RB_NT + tid];
+      if (tid >= o) x += sc[pin * RB_NT + tid - o];
+      sc[(1 - pin) * RB_NT + tid] = x;
+      pin ^= 1;
+      __syncthreads();
+    }
+    if (v < m) rb.base[v] = run + sc[pin * RB_NT + tid] - n;
+    run += sc[pin * RB_NT + RB_NT - 1];
+    __syncthreads();
+  }
+}
+
+// Groups the deferred particles of the sorted pass by destination tile: each
+// goes to its tile's first list position plus its rank there.
+template <int DIMS, int ORDER, typename R>
+__global__ void __launch_bounds__(256) k_rebin_scatter(KParams<R> P, const int* __restrict__ cell,
+                                                       const int* __restrict__ deferred, Rebin rb,
+                                                       DevFlags* flg) {
+  const int nd = (int)flg->ndefer;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nd; i += gridDim.x * blockDim.x) {
+    const int t = deferred_tile<DIMS, ORDER, R>(P, cell, deferred, i);
+    rb.list[rb.base[rb.tv[t]] + rb.rank[i]] = deferred[i];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0 && nd > 0) atomicAdd(&flg->rebinned, (unsigned long long)nd);
+}
+
 // Global-memory kernel for the deferred particles: the same gather, push,
 // move and deposit with fields read from and currents added to global
 // memory.  The list length is read on the device.
 template <int DIMS, int ORDER, typename R>
 __global__ void __launch_bounds__(256) k_push_deferred(KParams<R> P, DParts<R> pa, DFields<R> F,
                                                        const int* __restrict__ deferred,
+                                                       const unsigned* __restrict__ count,
                                                        DevFlags* flg) {
-  const int nd = (int)flg->ndefer;
+  const int nd = (int)*count;
   const int open0 = P.bc[0] == PIC_BC_OPEN, open1 = P.bc[1] == PIC_BC_OPEN;
   const int open2 = DIMS == 3 && P.bc[2] == PIC_BC_OPEN;
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < nd; t += gridDim.x * blockDim.x) {
@@ -503,11 +638,21 @@ __global__ void __launch_bounds__(256) k_push_deferred(KParams<R> P, DParts<R> p
 }
 
 // Zero J (n = 0: keep it, another species adds its current), the
-// deferred-list length and the tile counters before a push.
+// deferred-list lengths, the tile counters and the re-binned pass's counts
+// before a push.
 template <typename R>
-__global__ void k_push_prologue(R* a, R* b, R* c, long n, DevFlags* flg) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) flg->ndefer = 0u;
+__global__ void k_push_prologue(R* a, R* b, R* c, long n, DevFlags* flg, int* rb_cnt, int ntiles) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    flg->since_sort += flg->ndefer;
+    flg->ndefer = 0u;
+    flg->ndefer2 = 0u;
+    flg->rb_m = 0u;
+    flg->rb_next = 0u;
+    flg->rb_done = 0u;
+  }
   if (blockIdx.x == 0 && threadIdx.x < 8) flg->tile_next[threadIdx.x] = 0u;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < ntiles; i += gridDim.x * blockDim.x)
+    rb_cnt[i] = 0;
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
     a[i] = R(0);
     b[i] = R(0);
@@ -530,13 +675,13 @@ static int device_cus() {
 
 // Workgroups of the persistent tile kernel: as many as are resident at once
 // (compute units x workgroups per unit), at most 8 x the XCD range length.
-template <int DIMS, int ORDER, typename R>
+template <int DIMS, int ORDER, typename R, bool RB>
 static unsigned tile_grid(const KParams<R>& P) {
   using G = Geo<DIMS, ORDER, R>;
   static int occ = 0;
   if (occ == 0) {
     int b = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_push_tile<DIMS, ORDER, R>, G::NT, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_push_tile<DIMS, ORDER, R, RB>, G::NT, 0) !=
             hipSuccess ||
         b < 1)
       b = 1;
@@ -568,14 +713,34 @@ static int launch_pd(const pic_ctx* ctx, const pic_particles* p, const pic_field
     F.J[c] = (R*)f->J[c];
   }
   DevFlags* flg = (DevFlags*)(w + L.flags);
-  int* deferred = (int*)(w + L.tmp_cell);  // the sort's scratch is free during a push
+  // the sort's scratch is free during a push: deferred list, re-binning
+  int* deferred = (int*)(w + L.tmp_cell);
+  Rebin rb;
+  rb.cnt = (int*)(w + L.counts);
+  rb.tv = (int*)(w + L.rb_tv);
+  rb.nl = (int*)(w + L.rb_nl);
+  rb.base = (int*)(w + L.bstart);
+  rb.rank = (int*)(w + L.keys);
+  rb.list = (int*)(w + L.tmp_id);
+  rb.defer2 = (int*)(w + L.tmp_real);
   const long ncell = accumulate ? 0L : (long)P.n[0] * P.n[1] * P.n[2];
-  const long fb = (ncell + 255) / 256;
+  const long nz = ncell > P.ntiles ? ncell : (long)P.ntiles;
+  const long fb = (nz + 255) / 256;
   k_push_prologue<R><<<dim3((unsigned)(fb < 1 ? 1 : fb < 4096 ? fb : 4096)), dim3(256), 0, s>>>(
-      F.J[0], F.J[1], F.J[2], ncell, flg);
-  k_push_tile<DIMS, ORDER, R><<<dim3(tile_grid<DIMS, ORDER, R>(P)), dim3(G::NT), 0, s>>>(
-      P, pa, F, (const int*)(w + L.starts), deferred, flg);
-  k_push_deferred<DIMS, ORDER, R><<<dim3(1024), dim3(256), 0, s>>>(P, pa, F, deferred, flg);
+      F.J[0], F.J[1], F.J[2], ncell, flg, rb.cnt, P.ntiles);
+  k_push_tile<DIMS, ORDER, R, false><<<dim3(tile_grid<DIMS, ORDER, R, false>(P)), dim3(G::NT), 0, s>>>(
+      P, pa, F, (const int*)(w + L.starts), deferred, flg, rb);
+  if (ctx->rebin) {
+    k_rebin_count<DIMS, ORDER, R><<<dim3(512), dim3(RB_NT), 0, s>>>(P, pa.cell, deferred, rb, flg);
+    k_rebin_scatter<DIMS, ORDER, R><<<dim3(512), dim3(256), 0, s>>>(P, pa.cell, deferred, rb, flg);
+    k_push_tile<DIMS, ORDER, R, true><<<dim3(tile_grid<DIMS, ORDER, R, true>(P)), dim3(G::NT), 0, s>>>(
+        P, pa, F, (const int*)(w + L.starts), deferred, flg, rb);
+    k_push_deferred<DIMS, ORDER, R><<<dim3(1024), dim3(256), 0, s>>>(P, pa, F, rb.defer2, &flg->ndefer2,
+                                                                      flg);
+  } else {
+    k_push_deferred<DIMS, ORDER, R><<<dim3(1024), dim3(256), 0, s>>>(P, pa, F, deferred, &flg->ndefer,
+                                                                      flg);
+  }
   return (int)hipGetLastError();
 }
 

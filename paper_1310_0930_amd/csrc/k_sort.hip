@@ -92,7 +92,11 @@ __global__ void __launch_bounds__(COUNT_NT) k_sort_count(SortParams S, const int
                                                          int* __restrict__ counts, DevFlags* flg) {
   __shared__ int acc;
   const long c0 = spread_block(blockIdx.x, gridDim.x) * (long)(COUNT_NT * COUNT_PER);
-  if (c0 == 0 && threadIdx.x == 0) flg->qmax = 0u;  // the scatter takes the new maximum
+  if (c0 == 0 && threadIdx.x == 0) {
+    flg->qmax = 0u;  // the scatter takes the new maximum
+    flg->ndefer = 0u;  // a new sort interval starts
+    flg->since_sort = 0ull;
+  }
   const int lane = threadIdx.x & 63;
   const int key0 = c0 < np ? tile_key(S, cell[c0], ncell) : -1;
   if (threadIdx.x == 0) acc = 0;

@@ -32,6 +32,10 @@ WsLayout ws_layout(const pic_ctx* ctx, int64_t np) {
   off = align256(off + sizeof(int) * (nbins + 1));
   L.bsum = off;
   off = align256(off + sizeof(int) * (nbins / 1024 + 1));
+  L.rb_tv = off;
+  off = align256(off + sizeof(int) * (size_t)ctx->ntiles);
+  L.rb_nl = off;
+  off = align256(off + sizeof(int) * (size_t)ctx->ntiles);
   L.mur_len = (size_t)mur_len(ctx->cfg);
   L.mur = off;
   off = align256(off + R * L.mur_len);
@@ -182,6 +186,8 @@ int pic_create(const pic_config* cfg, pic_ctx** out) {
   ctx->cfg.tile[2] = T[2];
   ctx->cfg.drift = A;
   ctx->steps_done = 0;
+  ctx->rebin = true;
+  ctx->pushes_since_sort = 0;
   ctx->sorted_cell = nullptr;
   ctx->sorted_ws = nullptr;
   ctx->sorted_np = -1;
@@ -236,14 +242,21 @@ int pic_sort(pic_ctx* ctx, pic_particles* p, void* ws, void* stream) {
   int v = check_particles(ctx, p);
   if (v) return v;
   if ((v = ensure_device(ctx))) return v;
+  // Whether the pushes since the previous sort (in this workspace) left any
+  // particle outside the sorted tile pass: read before the sort clears the
+  // count, alongside the live count's read-back below.
+  const bool judge = ctx->pushes_since_sort > 0 && ctx->sorted_ws == ws && p->np > 0;
+  DevFlags fh;
+  hipStream_t s = (hipStream_t)stream;
+  if (judge && hipMemcpyAsync(&fh, ws, sizeof(fh), hipMemcpyDeviceToHost, s) != hipSuccess)
+    return PIC_EHIP;
   ctx->sorted_cell = nullptr;  // bins are valid only once the sort has completed
-  v = hip_status(launch_sort(ctx, p, ws, (hipStream_t)stream));
+  v = hip_status(launch_sort(ctx, p, ws, s));
   if (v != PIC_OK) return v;
   if (p->np > 0) {
     // compaction: the dead bin starts at the live count, which becomes np
     int32_t live = 0;
     const WsLayout L = ws_layout(ctx, p->np);
-    hipStream_t s = (hipStream_t)stream;
     if (hipMemcpyAsync(&live, (const char*)ws + L.starts + sizeof(int32_t) * (size_t)ctx->ntiles,
                        sizeof(live), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
@@ -251,6 +264,8 @@ int pic_sort(pic_ctx* ctx, pic_particles* p, void* ws, void* stream) {
     if (live < 0 || live > p->np) return PIC_EHIP;
     p->np = live;
   }
+  if (judge) ctx->rebin = fh.since_sort + fh.ndefer > 0;
+  ctx->pushes_since_sort = 0;
   ctx->sorted_cell = p->cell;
   ctx->sorted_ws = ws;
   ctx->sorted_np = p->np;
@@ -265,6 +280,7 @@ int pic_push_deposit(pic_ctx* ctx, pic_particles* p, const pic_fields* f, void* 
   if (ctx->sorted_cell != p->cell || ctx->sorted_ws != ws || ctx->sorted_np != p->np)
     return PIC_ESTATE;
   if ((v = ensure_device(ctx))) return v;
+  ctx->pushes_since_sort += 1;
   return hip_status(launch_push_deposit(ctx, p, f, ws, (hipStream_t)stream, false));
 }
 
@@ -277,6 +293,7 @@ int pic_push_deposit_add(pic_ctx* ctx, pic_particles* p, const pic_fields* f, vo
   if (ctx->sorted_cell != p->cell || ctx->sorted_ws != ws || ctx->sorted_np != p->np)
     return PIC_ESTATE;
   if ((v = ensure_device(ctx))) return v;
+  ctx->pushes_since_sort += 1;
   return hip_status(launch_push_deposit(ctx, p, f, ws, (hipStream_t)stream, true));
 }
 
@@ -533,6 +550,20 @@ int pic_read_flags(pic_ctx* ctx, void* ws, int clear, uint32_t* flags, int64_t* 
   if (flags) *flags = h.flags;
   if (n_slowpath) *n_slowpath = (int64_t)h.slowpath;
   return h.flags ? PIC_EDEVICE : PIC_OK;
+}
+
+int pic_read_push_counts(pic_ctx* ctx, void* ws, int64_t* n_rebinned, int64_t* n_slowpath,
+                         void* stream) {
+  if (!ctx || !ws) return PIC_EINVAL;
+  int v = ensure_device(ctx);
+  if (v) return v;
+  DevFlags h;
+  hipStream_t s = (hipStream_t)stream;
+  if (hipMemcpyAsync(&h, ws, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess) return PIC_EHIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return PIC_EHIP;
+  if (n_rebinned) *n_rebinned = (int64_t)h.rebinned;
+  if (n_slowpath) *n_slowpath = (int64_t)h.slowpath;
+  return PIC_OK;
 }
 
 const char* pic_strerror(int status) {

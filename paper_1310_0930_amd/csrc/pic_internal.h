@@ -128,18 +128,44 @@ struct DFields {
 // Sticky flags and counters at the head of the workspace.
 struct DevFlags {
   unsigned int flags;
-  unsigned int ndefer;          // particles deferred to the global-memory kernel this push
-  unsigned long long slowpath;  // total deferred pushes since the last clear
+  unsigned int ndefer;          // particles the sorted tile pass left to the re-binned pass this push
+  unsigned long long slowpath;  // total global-memory pushes since the last clear
+  unsigned long long rebinned;  // total pushes handed to the re-binned pass since the last clear
   // Written by the sort (not cleared with the flags): bit pattern of the
   // largest |q| (as float) over the per-particle charges it moved.
   unsigned int qmax;
-  unsigned int pad1;
+  unsigned int ndefer2;         // particles left to the global-memory kernel this push
   // Work counters of the persistent push: tiles taken so far from each
   // XCD's tile range (cleared before every push).
   unsigned int tile_next[8];
-  unsigned long long pad2[1];
+  // Re-binned pass (cleared before every push): destination tiles holding
+  // re-binned particles, claims of them, and workgroups of the sorted pass
+  // that have finished.
+  unsigned int rb_m;
+  unsigned int rb_next;
+  unsigned int rb_done;
+  unsigned int pad0;
+  // particles the sorted pass left, summed over the pushes since the last
+  // sort (each push's prologue adds the previous push's ndefer; the sort's
+  // count kernel clears both)
+  unsigned long long since_sort;
+  unsigned int pad[10];
 };
-static_assert(sizeof(DevFlags) == 64, "DevFlags layout");
+static_assert(sizeof(DevFlags) == 128, "DevFlags layout");
+
+// Particles that drifted beyond the allowance of the tile they were sorted
+// into, re-binned by the tile of their current cell for a second tile pass
+// (device pointers into the workspace; the sort's scratch is free during a
+// push).
+struct Rebin {
+  int* cnt;     // int32[ntiles]  re-binned particles per destination tile (zeroed per push)
+  int* tv;      // int32[ntiles]  slot of a destination tile in nl
+  int* nl;      // int32[ntiles]  destination tiles in order of their first particle
+  int* base;    // int32[ntiles]  first list position of each slot
+  int* rank;    // int32[np]      rank of each deferred entry within its destination tile
+  int* list;    // int32[np]      the deferred particles grouped by destination tile
+  int* defer2;  // int32[np]      particles left to the global-memory kernel
+};
 
 // ------------------------------------------------------------------ workspace
 struct WsLayout {
@@ -148,6 +174,8 @@ struct WsLayout {
   size_t counts;     // int32[nbins]        bin counts / scatter cursors
   size_t bstart;     // int32[nbins + 1]    bin starts
   size_t bsum;       // int32[nbins / 1024 + 1]  scan block sums
+  size_t rb_tv;      // int32[ntiles]       re-binned pass: slot of each destination tile
+  size_t rb_nl;      // int32[ntiles]       re-binned pass: destination tiles
   size_t keys;       // int32[np]           tile of each particle, then its in-tile bin and cell
   size_t order;      // int32[1024]         a tile's cells listed by bank residue
   size_t tmp_cell;   // int32[np]
@@ -171,6 +199,11 @@ struct pic_ctx {
   int ntiles;
   int tile[3];
   int64_t steps_done;      // steps taken through pic_step (drives sort_every)
+  // Re-binned push pass on or off: decided at each sort from whether the
+  // pushes since the previous sort left any particle outside the sorted
+  // tile pass (on for a new context).
+  bool rebin;
+  int64_t pushes_since_sort;
   // sorted-state tracking: pic_push_deposit needs bins that match the arrays
   const void* sorted_cell;
   const void* sorted_ws;

@@ -112,6 +112,8 @@ _SIGS = {
                                   C.c_void_p], C.c_int),
     "pic_read_flags": ([C.c_void_p, C.c_void_p, C.c_int, C.POINTER(C.c_uint32),
                         C.POINTER(C.c_int64), C.c_void_p], C.c_int),
+    "pic_read_push_counts": ([C.c_void_p, C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                              C.c_void_p], C.c_int),
     "pic_strerror": ([C.c_int], C.c_char_p),
 }
 
@@ -308,6 +310,14 @@ def pic_read_flags(ctx, ws, clear=False, stream=None):
     if st not in (PIC_OK, PIC_EDEVICE):
         _check(st, "pic_read_flags")
     return f.value, s.value
+
+
+def pic_read_push_counts(ctx, ws, stream=None):
+    r = C.c_int64()
+    s = C.c_int64()
+    _check(lib().pic_read_push_counts(ctx, C.c_void_p(ws), C.byref(r), C.byref(s), _stream(stream)),
+           "pic_read_push_counts")
+    return r.value, s.value
 
 
 # ---------------------------------------------------------------- simulation
@@ -535,3 +545,7 @@ class Simulation:
 
     def read_flags(self, clear=False):
         return pic_read_flags(self.ctx, self.ws.data_ptr(), clear, self.stream)
+
+    def read_push_counts(self):
+        """(re-binned, global-memory) pushes since the flags were last cleared."""
+        return pic_read_push_counts(self.ctx, self.ws.data_ptr(), self.stream)

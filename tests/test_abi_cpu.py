@@ -96,6 +96,7 @@ def test_null_arguments():
     assert lib.pic_deposit_rho(None, None, None, None, None) == P.PIC_EINVAL
     assert lib.pic_diagnostics(None, None, None, None, None, None, None, None, None, None) == P.PIC_EINVAL
     assert lib.pic_read_flags(None, None, 0, None, None, None) == P.PIC_EINVAL
+    assert lib.pic_read_push_counts(None, None, None, None, None) == P.PIC_EINVAL
     assert lib.pic_push_deposit_add(None, None, None, None, None) == P.PIC_EINVAL
     assert lib.pic_deposit_rho_add(None, None, None, None, None) == P.PIC_EINVAL
     assert lib.pic_step_species(0, None, None, None, None, 1, None) == P.PIC_EINVAL
