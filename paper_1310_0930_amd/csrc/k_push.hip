@@ -537,8 +537,11 @@ __device__ __forceinline__ int deferred_tile(const KParams<R>& P, const int* __r
 // (the tile of their current cell), giving each its rank there and listing
 // the destination tiles in order of their first particle; the last
 // workgroup to finish turns the counts into first list positions
-// (exclusive prefix sum in the order of rb.nl).  Every thread fences its
-// own writes before its workgroup counts itself as finished.
+// (exclusive prefix sum in the order of rb.nl).  Consecutive entries of the
+// list mostly come from one tile and go to one, so the lanes of a
+// wavefront that share a destination take their ranks with one atomic.
+// Every thread fences its own writes before its workgroup counts itself as
+// finished.
 constexpr int RB_NT = 256;
 template <int DIMS, int ORDER, typename R>
 __global__ void __launch_bounds__(RB_NT) k_rebin_count(KParams<R> P, const int* __restrict__ cell,
@@ -547,14 +550,29 @@ __global__ void __launch_bounds__(RB_NT) k_rebin_count(KParams<R> P, const int* 
   __shared__ int sc[2 * RB_NT];
   __shared__ int s_last;
   const int nd = (int)flg->ndefer;
-  for (int i = blockIdx.x * RB_NT + threadIdx.x; i < nd; i += gridDim.x * RB_NT) {
-    const int t = deferred_tile<DIMS, ORDER, R>(P, cell, deferred, i);
-    const int r = atomicAdd(&rb.cnt[t], 1);
-    rb.rank[i] = r;
-    if (r == 0) {
-      const unsigned v = atomicAdd(&flg->rb_m, 1u);
-      rb.nl[v] = t;
-      rb.tv[t] = (int)v;
+  if (nd == 0) return;  // (nothing to re-bin: the re-binned pass finds no tile)
+  const int lane = threadIdx.x & 63;
+  for (int i0 = blockIdx.x * RB_NT + (threadIdx.x & ~63); i0 < nd; i0 += gridDim.x * RB_NT) {
+    const int i = i0 + lane;
+    const bool act = i < nd;
+    const int t = act ? deferred_tile<DIMS, ORDER, R>(P, cell, deferred, i) : -1;
+    unsigned long long todo = __ballot(act);
+    while (todo) {
+      const int l0 = __ffsll((long long)todo) - 1;
+      const int t0 = __shfl(t, l0, 64);
+      const unsigned long long same = __ballot(act && t == t0);
+      int r0 = 0;
+      if (lane == l0) {
+        r0 = atomicAdd(&rb.cnt[t0], (int)__popcll(same));
+        if (r0 == 0) {
+          const unsigned v = atomicAdd(&flg->rb_m, 1u);
+          rb.nl[v] = t0;
+          rb.tv[t0] = (int)v;
+        }
+      }
+      r0 = __shfl(r0, l0, 64);
+      if (act && t == t0) rb.rank[i] = r0 + (int)__popcll(same & ((1ull << lane) - 1ull));
+      todo &= ~same;
     }
   }
   __threadfence();
@@ -731,7 +749,7 @@ static int launch_pd(const pic_ctx* ctx, const pic_particles* p, const pic_field
   k_push_tile<DIMS, ORDER, R, false><<<dim3(tile_grid<DIMS, ORDER, R, false>(P)), dim3(G::NT), 0, s>>>(
       P, pa, F, (const int*)(w + L.starts), deferred, flg, rb);
   if (ctx->rebin) {
-    k_rebin_count<DIMS, ORDER, R><<<dim3(512), dim3(RB_NT), 0, s>>>(P, pa.cell, deferred, rb, flg);
+    k_rebin_count<DIMS, ORDER, R><<<dim3(256), dim3(RB_NT), 0, s>>>(P, pa.cell, deferred, rb, flg);
     k_rebin_scatter<DIMS, ORDER, R><<<dim3(512), dim3(256), 0, s>>>(P, pa.cell, deferred, rb, flg);
     k_push_tile<DIMS, ORDER, R, true><<<dim3(tile_grid<DIMS, ORDER, R, true>(P)), dim3(G::NT), 0, s>>>(
         P, pa, F, (const int*)(w + L.starts), deferred, flg, rb);
