@@ -189,7 +189,7 @@ def test_w3d_256_cubic_twenty_steps(rb):
     at every check; FP32 within 1e-5 over the first 12 steps and within
     max(1e-5, 3 x its conditioning floor) after that (the a0 = 4 pulse
     amplifies storage rounding as in the 512x256 case)."""
-    w = I.WORKLOADS["w3d_256_cubic_laser"]
+    w = I.WORKLOADS["w3d_256_cubic_laser"].with_(sort_every=4)
     pl, E, B = inputs_for(w)
     checks = list(range(4, 21, 4))
     refs, floors = _w3d_256_reference(w, pl, E, B, checks)
@@ -218,7 +218,8 @@ def test_w3d_256_cubic_narrow_two_hundred_steps():
     4 steps) on a 256x24x24 grid (1.2M particles) for all 200 steps, FP64
     and FP32 against the oracle at every 40th step, within max(bar, 3 x the
     conditioning floor of each precision)."""
-    w = I.WORKLOADS["w3d_256_cubic_laser"].with_(n=(256, 24, 24), seed=I.SEED_BASE + 90)
+    w = I.WORKLOADS["w3d_256_cubic_laser"].with_(n=(256, 24, 24), seed=I.SEED_BASE + 90,
+                                                  sort_every=4)
     pl, E, B = inputs_for(w)
     say("case", w.name, w.n3, "np", pl.np, "steps", w.steps)
     sims = {rb: gpu_sim(w, rb, pl, E, B) for rb in (8, 4)}

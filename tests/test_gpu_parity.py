@@ -145,6 +145,26 @@ def test_parity_relativistic_drift_rebinned_pass(rb):
 
 
 @pytest.mark.parametrize("rb", [8, 4])
+@pytest.mark.parametrize("dims,order,bc", [(3, 1, (0, 0, 0)), (3, 3, (0, 1, 0)), (3, 4, (0, 0, 1)),
+                                           (2, 2, (0, 1)), (2, 4, (1, 0))])
+def test_parity_rebinned_pass_every_form(dims, order, bc, rb):
+    """Hot plasma (u_th = 1) sorted once and pushed for 14 steps, so that
+    particles drift beyond their tiles' allowance and take the re-binned
+    tile pass, at orders 1-4, in 2D and 3D, next to open faces: every
+    particle and field sample against the oracle."""
+    n = (24, 20, 12) if dims == 3 else (48, 40)
+    w = I.Workload("w_rebin", dims, n, (0.2,) * dims, order, 4, 1.0, 14, bc=bc,
+                   seed=I.SEED_BASE + 60 + 10 * dims + order)
+    sim, ref = _run(w, rb, w.steps, sort_every=1000)
+    flags, nslow = sim.read_flags()
+    nreb, _ = sim.read_push_counts()
+    say("re-binned", dims, order, bc, rb, "re-binned pushes", nreb, "slow path pushes", nslow)
+    assert flags == 0
+    assert nreb > 0
+    _check(compare(w, sim, ref), rb, "re-binned pass")
+
+
+@pytest.mark.parametrize("rb", [8, 4])
 def test_parity_global_memory_path(rb):
     """Relativistic particles (u_th = 2) on a grid four times finer along x
     than across, at 0.95 of the Courant step: many move half a cell or more
