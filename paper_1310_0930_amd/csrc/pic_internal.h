@@ -128,13 +128,13 @@ struct DFields {
 // Sticky flags and counters at the head of the workspace.
 struct DevFlags {
   unsigned int flags;
-  unsigned int ndefer;          // particles the sorted tile pass left to the re-binned pass this push
+  unsigned int ndefer;          // particles the sorted tile pass left this push (deferred list)
   unsigned long long slowpath;  // total global-memory pushes since the last clear
   unsigned long long rebinned;  // total pushes handed to the re-binned pass since the last clear
   // Written by the sort (not cleared with the flags): bit pattern of the
   // largest |q| (as float) over the per-particle charges it moved.
   unsigned int qmax;
-  unsigned int ndefer2;         // particles left to the global-memory kernel this push
+  unsigned int ndefer2;         // particles the re-binned pass left to the global-memory kernel
   // Work counters of the persistent push: tiles taken so far from each
   // XCD's tile range (cleared before every push).
   unsigned int tile_next[8];
