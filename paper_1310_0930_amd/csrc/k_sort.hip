@@ -14,7 +14,11 @@
 // relative to the cell, so that the 64 lanes of a wavefront read and add at
 // their cells' bases plus one common offset.  Within a class the particles
 // cycle through the LDS bank residues of their cells (k_sort_place), so that
-// those bases fall on distinct banks.  The tile-level pass aggregates runs
+// those bases fall on distinct banks.  Particles move between sorts and the
+// layout decays, so the class and cell used for the placement are those a
+// straight-line estimate gives half a sort interval ahead (the particle's
+// tile is still that of its present cell); the layout is then best in the
+// middle of the interval rather than at its start.  The tile-level pass aggregates runs
 // of equal tiles inside a wavefront (particles stay in their tile for many
 // steps), one global atomic per run; the placement runs in LDS, one
 // workgroup per tile.
@@ -35,6 +39,9 @@ struct SortParams {
   // row and plane strides (elements) of the push kernel's LDS region whose
   // element indices decide the lanes' banks (region_strides_t)
   int rs1, rs2;
+  // placement estimate: cells moved per unit of u_d over half a sort
+  // interval, ((sort_every - 1) / 2) dt / dx_d
+  double hdx[3];
 };
 
 __device__ __forceinline__ int tile_key(const SortParams& S, int cl, int ncell) {
@@ -335,7 +342,10 @@ __global__ void __launch_bounds__(ORDER_NT) k_sort_order(SortParams S, int* __re
 // Placement of one tile's particles (one workgroup per tile) from the
 // scatter's copy back into the particle arrays.  Pass 1 gives every particle
 // its class and its rank among the particles of its (cell, class), from LDS
-// counters.  Within a class the particles are ranked by (k, r): r is the
+// counters; class and cell are those of the position estimated half a sort
+// interval ahead, x_d + clamp(u_d, -1, 1) hdx_d (|u_d| for the speed below
+// c, its bound above), rounded step by step in double so that a host can
+// restate it exactly, or the present ones when that cell leaves the tile.  Within a class the particles are ranked by (k, r): r is the
 // residue of the particle's cell, k the number of the class's particles of
 // the same residue before it (cells in cell order, a cell's particles in
 // rank order).  The class cycles through the residues it holds, so any RES
@@ -388,17 +398,21 @@ __global__ void __launch_bounds__(PLACE_NT) k_sort_place(SortArrays<R> A, SortPa
   constexpr int PB1 = 4;
   for (int i0 = beg + threadIdx.x; i0 < end; i0 += PB1 * PLACE_NT) {
     int pc[PB1];
-    R po[PB1][3];
+    R po[PB1][3], pu[PB1][3];
 #pragma unroll
     for (int k = 0; k < PB1; ++k) {
       const int i = i0 + k * PLACE_NT;
       pc[k] = 0;
       po[k][0] = po[k][1] = po[k][2] = R(0);
+      pu[k][0] = pu[k][1] = pu[k][2] = R(0);
       if (i < end) {
         pc[k] = A.t_cell[i];
 #pragma unroll
         for (int d = 0; d < 3; ++d)
-          if (d < dims) po[k][d] = A.t_off[d][i];
+          if (d < dims) {
+            po[k][d] = A.t_off[d][i];
+            pu[k][d] = A.t_u[d][i];
+          }
       }
     }
 #pragma unroll
@@ -414,10 +428,31 @@ __global__ void __launch_bounds__(PLACE_NT) k_sort_place(SortArrays<R> A, SortPa
           cy = (int)(rest - r2 * S.n[1]);
           cz = (int)r2;
         }
-        const int cell =
-            (cx - tx * S.T[0]) + S.T[0] * ((cy - ty * S.T[1]) + S.T[1] * (cz - tz * S.T[2]));
-        int cls = (po[k][0] >= R(0.5) ? 1 : 0) | (po[k][1] >= R(0.5) ? 2 : 0);
-        if (dims == 3) cls |= po[k][2] >= R(0.5) ? 4 : 0;
+        const int lc[3] = {cx - tx * S.T[0], cy - ty * S.T[1], cz - tz * S.T[2]};
+        int lp[3] = {lc[0], lc[1], lc[2]};
+        double op[3] = {0.0, 0.0, 0.0};
+        bool in = true;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          if (d < dims) {
+            const double v = fmin(fmax((double)pu[k][d], -1.0), 1.0);
+            const double x = __dadd_rn((double)po[k][d], __dmul_rn(v, S.hdx[d]));
+            const double f = floor(x);
+            lp[d] = lc[d] + (int)f;
+            op[d] = x - f;
+            in = in && lp[d] >= 0 && lp[d] < S.T[d];
+          }
+        }
+        if (!in) {
+#pragma unroll
+          for (int d = 0; d < 3; ++d) {
+            lp[d] = lc[d];
+            op[d] = (double)po[k][d];
+          }
+        }
+        const int cell = lp[0] + S.T[0] * (lp[1] + S.T[1] * lp[2]);
+        int cls = (op[0] >= 0.5 ? 1 : 0) | (op[1] >= 0.5 ? 2 : 0);
+        if (dims == 3) cls |= op[2] >= 0.5 ? 4 : 0;
         const int key = cls * TILE_CELLS_MAX + cell;
         const int rank = atomicAdd(&cnt[key], 1);
         scratch[i] = (rank << 12) | key;
@@ -632,6 +667,7 @@ static int launch_sort_t(const pic_ctx* ctx, const pic_particles* p, void* ws, h
     S.ntile[d] = ctx->ntile[d];
   }
   S.ntiles = ctx->ntiles;
+  for (int d = 0; d < 3; ++d) S.hdx[d] = d < c.dims ? 0.5 * (c.sort_every - 1) * c.dt / c.dx[d] : 0.0;
   region_strides<R>(c.dims, c.order, S);
   S.dn0.init((uint32_t)S.n[0]);
   S.dn1.init((uint32_t)S.n[1]);

@@ -411,10 +411,28 @@ def _check_sorted(w, rb, pl, st):
     # (single precision) or the current region (double) (32 banks), k the
     # number of the class's particles with the same
     # residue before it, cells taken in cell order.  Particles of one cell are interchangeable, so the cell
-    # sequence of every class is unique.
-    o = st["off"]
-    cls = sum((o[d] >= 0.5).astype(np.int64) << d for d in range(D))
-    lx, ly, lz = cx % T, cy % T, cz % TZ
+    # sequence of every class is unique.  Class and cell are those of the
+    # position estimated half a sort interval ahead, o_d + clamp(u_d, -1, 1)
+    # ((sort_every - 1) / 2) dt / dx_d, each operation rounded in double as
+    # the sort does it, or the present ones when that cell leaves the tile.
+    o, u = st["off"], st["u"]
+    lc = [cx % T, cy % T, cz % TZ]
+    tl = [T, T, TZ]
+    lp = [x.copy() for x in lc]
+    op = [np.zeros(len(c)) for _ in range(3)]
+    inside = np.ones(len(c), dtype=bool)
+    for d in range(D):
+        hdx = 0.5 * (w.sort_every - 1) * w.dt / w.dx3[d]
+        x = o[d] + np.clip(u[d], -1.0, 1.0) * hdx
+        f = np.floor(x)
+        lp[d] = lc[d] + f.astype(np.int64)
+        op[d] = x - f
+        inside &= (lp[d] >= 0) & (lp[d] < tl[d])
+    for d in range(3):
+        lp[d] = np.where(inside, lp[d], lc[d])
+        op[d] = np.where(inside, op[d], o[d] if d < D else 0.0)
+    cls = sum((op[d] >= 0.5).astype(np.int64) << d for d in range(D))
+    lx, ly, lz = lp
     lcell = lx + T * (ly + T * lz)
     nres = 32
     resid = (lx + rx * ly + plane * lz) % nres
