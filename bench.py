@@ -79,7 +79,9 @@ def lds_replay(w, real_bytes, iters=64):
     """LDS cycles of the push kernel's access patterns (quadratic 3D, 8^3
     tiles) replayed by the LDS probe (lds_probe_pattern) for the lane layouts
     that the tile sort produces from this workload's plasma (its first 16 z
-    planes: two layers of tiles, the first 64 tiles), and for the ideal
+    planes: two layers of tiles, the first 64 tiles), with the particles at
+    the positions the sort places them by (half a sort interval ahead on a
+    straight line, which is where the layout is meant to be best), and for the ideal
     layout (each 32 consecutive lanes on 32 distinct bank residues, one
     class).  CU cycles per 64-particle batch: the gather (six 27-node
     stencils) and the current deposit (54 adds of one virtual segment)."""
@@ -100,13 +102,25 @@ def lds_replay(w, real_bytes, iters=64):
     sim.load(I.make_plasma(w, slabs=range(16), quiet=False), None, None, with_id=False)
     sim.sort()
     st = sim.download()
-    c, o = st["cell"], st["off"]
+    c, o, u = st["cell"], st["off"], st["u"]
     n0, n1 = w.n3[0], w.n3[1]
     cx, cy, cz = c % n0, (c // n0) % n1, c // (n0 * n1)
     key = cx // 8 + (n0 // 8) * (cy // 8 + (n1 // 8) * (cz // 8))
-    cls = (o[0] >= 0.5).astype(np.int64) | ((o[1] >= 0.5).astype(np.int64) << 1) | \
-        ((o[2] >= 0.5).astype(np.int64) << 2)
-    lane = region_cell(cx % 8, cy % 8, cz % 8) | (cls << 16)
+    # the layout the sort aims at: every particle moved on the straight line
+    # the sort estimates, half a sort interval ahead, inside its tile
+    lc = [cx % 8, cy % 8, cz % 8]
+    lp, op, inside = [], [], np.ones(len(c), dtype=bool)
+    for d in range(3):
+        x = o[d] + np.clip(u[d], -1.0, 1.0) * (0.5 * (w.sort_every - 1) * w.dt / w.dx3[d])
+        f = np.floor(x)
+        lp.append(lc[d] + f.astype(np.int64))
+        op.append(x - f)
+        inside &= (lp[d] >= 0) & (lp[d] < 8)
+    lp = [np.where(inside, lp[d], lc[d]) for d in range(3)]
+    op = [np.where(inside, op[d], o[d]) for d in range(3)]
+    cls = (op[0] >= 0.5).astype(np.int64) | ((op[1] >= 0.5).astype(np.int64) << 1) | \
+        ((op[2] >= 0.5).astype(np.int64) << 2)
+    lane = region_cell(lp[0], lp[1], lp[2]) | (cls << 16)
     starts = np.searchsorted(key, np.arange(key.max() + 2))
     pats = []
     for t in range(min(64, int(key.max()) + 1)):
