@@ -166,8 +166,11 @@ int pic_workspace_bytes(const pic_ctx* ctx, int64_t np, size_t* bytes);
  * compacted away: p->np is lowered to the number of live particles, which
  * fill slots 0 .. np-1; the contents of the slots from the new np up to the
  * old one are unspecified.  Reading the live count back synchronises
- * `stream`.  Must precede pic_push_deposit.  This is the data layout change
- * that makes the deposit local; it does not change physics. */
+ * `stream`.  Must precede pic_push_deposit.  Inside a tile the particles are
+ * ordered by half-cell class and LDS bank residue of the position a straight
+ * line gives (sort_every - 1) / 2 steps ahead (the middle of the interval to
+ * the next sort).  This is the data layout change that makes the deposit
+ * local; it does not change physics. */
 int pic_sort(pic_ctx* ctx, pic_particles* p, void* ws, void* stream);
 
 /* One gather + Boris push + move + split + charge-conserving deposit pass
