@@ -738,7 +738,7 @@ def main():
         ach = ab / (r["push_ms_mean"] * 1e-3) / 1e9
         return {"bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic_from_profile(w.name, real),
-                "kernel": "k_push_tile (timed with its J-zeroing prologue and deferred-list kernel)",
+                "kernel": "k_push_tile (timed with its J-zeroing prologue, the re-binned pass where it is on, and the deferred-list kernel)",
                 "alg_bytes_per_launch": ab,
                 "avg_launch_ms": round(r["push_ms_mean"], 5)}
 
