@@ -165,6 +165,35 @@ def test_parity_rebinned_pass_every_form(dims, order, bc, rb):
 
 
 @pytest.mark.parametrize("rb", [8, 4])
+def test_rebinned_pass_follows_the_last_sort_interval(rb):
+    """The re-binned pass is switched at each sort by whether the pushes
+    since the previous sort left any particle: two pushes after a sort (a
+    particle moves less than half a cell per push, so none can leave the
+    one-cell allowance) switch it off, and the drifting particles of the
+    next 12 pushes go to global memory; that switches it on again for the
+    12 pushes after the next sort.  Every particle and field sample against
+    the oracle after the 26 steps."""
+    w = I.Workload("w_switch", 3, (24, 20, 12), (0.2,) * 3, 2, 4, 1.0, 26, seed=I.SEED_BASE + 95)
+    pl, E, B = inputs_for(w)
+    sim = gpu_sim(w, rb, pl, E, B, sort_every=1 << 20)
+    counts = []
+    for pushes in (2, 12, 12):
+        sim.sort()
+        for _ in range(pushes):
+            sim.push_deposit()
+            sim.field_advance()
+        counts.append(sim.read_push_counts())
+    torch.cuda.synchronize()
+    say("switch", rb, "(re-binned, global) after each interval", counts)
+    assert counts[0] == (0, 0)
+    assert counts[1][0] == 0 and counts[1][1] > 0  # off: the drifters went to global memory
+    assert counts[2][0] > 0  # on again
+    ref = oracle_state(w, pl, E, B)
+    ref.step(w.steps, nthreads=oracle_threads())
+    _check(compare(w, sim, ref), rb, "re-binned pass switching")
+
+
+@pytest.mark.parametrize("rb", [8, 4])
 def test_parity_global_memory_path(rb):
     """Relativistic particles (u_th = 2) on a grid four times finer along x
     than across, at 0.95 of the Courant step: many move half a cell or more
