@@ -209,10 +209,62 @@ struct SortArrays {
   int* t_id;
 };
 
+// Cells of a tile (at most; 8^3 in 3D, 16^2 in 2D).
+constexpr int TILE_CELLS_MAX = 512;
+
+// In-tile placement key of a live particle of tile t: its class (the half
+// of the cell along each axis) and its cell within the tile, both of the
+// position a straight line gives half a sort interval ahead,
+// x_d + clamp(u_d, -1, 1) hdx_d (|u_d| for the speed below c, its bound
+// above), rounded operation by operation in double so that a host can
+// restate it exactly; the present cell and offsets when that cell leaves
+// the tile.
 template <typename R>
-__global__ void k_sort_scatter(SortArrays<R> A, long np, int ncell, int dims,
+__device__ __forceinline__ int placement_key(const SortParams& S, int t, int cl, const R* o,
+                                             const R* u) {
+  const int tx = t % S.ntile[0], ty = (t / S.ntile[0]) % S.ntile[1], tz = t / (S.ntile[0] * S.ntile[1]);
+  const uint32_t rest = S.dn0.div((uint32_t)cl);
+  const int cx = cl - (int)rest * S.n[0];
+  int cy = (int)rest, cz = 0;
+  if (S.dims == 3) {
+    const uint32_t r2 = S.dn1.div(rest);
+    cy = (int)(rest - r2 * S.n[1]);
+    cz = (int)r2;
+  }
+  const int lc[3] = {cx - tx * S.T[0], cy - ty * S.T[1], cz - tz * S.T[2]};
+  int lp[3] = {lc[0], lc[1], lc[2]};
+  double op[3] = {0.0, 0.0, 0.0};
+  bool in = true;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    if (d < S.dims) {
+      const double v = fmin(fmax((double)u[d], -1.0), 1.0);
+      const double x = __dadd_rn((double)o[d], __dmul_rn(v, S.hdx[d]));
+      const double f = floor(x);
+      lp[d] = lc[d] + (int)f;
+      op[d] = x - f;
+      in = in && lp[d] >= 0 && lp[d] < S.T[d];
+    }
+  }
+  if (!in) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      lp[d] = lc[d];
+      op[d] = (double)o[d];
+    }
+  }
+  int cls = (op[0] >= 0.5 ? 1 : 0) | (op[1] >= 0.5 ? 2 : 0);
+  if (S.dims == 3) cls |= op[2] >= 0.5 ? 4 : 0;
+  return cls * TILE_CELLS_MAX + lp[0] + S.T[0] * (lp[1] + S.T[1] * lp[2]);
+}
+
+// Copies every particle to its tile's range of the scratch arrays (in the
+// order the atomics give) and records its in-tile placement key there.
+template <typename R>
+__global__ void k_sort_scatter(SortArrays<R> A, SortParams S, long np, int ncell,
                                const int* __restrict__ keys, int* __restrict__ cursor,
-                               DevFlags* flg) {
+                               int* __restrict__ pkey, DevFlags* flg) {
+  const int dims = S.dims;
   const long p = spread_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   const bool in = p < np;
   // the payload is loaded first, so that its latency overlaps the cursor
@@ -253,7 +305,9 @@ __global__ void k_sort_scatter(SortArrays<R> A, long np, int ncell, int dims,
   }
   if (!in) return;
   const long dst = (long)base + (lane - head);
-  A.t_cell[dst] = (cl >= 0 && cl < ncell) ? cl : -1;
+  const bool live = cl >= 0 && cl < ncell;
+  if (live) pkey[dst] = placement_key<R>(S, key, cl, o, u);
+  A.t_cell[dst] = live ? cl : -1;
   for (int d = 0; d < dims; ++d) A.t_off[d][dst] = o[d];
   for (int c = 0; c < 3; ++c) A.t_u[c][dst] = u[c];
   if (A.id) A.t_id[dst] = idv;
@@ -304,7 +358,6 @@ struct PVal {
 // order[0 .. ncells) = cells sorted by (residue, cell),
 // order[TILE_CELLS_MAX + r] = first entry of residue r (r <= RES).
 constexpr int ORDER_NT = 512;
-constexpr int TILE_CELLS_MAX = 512;
 constexpr int RES = 32;
 static_assert(RES <= 32, "residue masks are 32-bit words");
 __device__ __forceinline__ int cell_residue(const SortParams& S, int lc) {
@@ -342,10 +395,9 @@ __global__ void __launch_bounds__(ORDER_NT) k_sort_order(SortParams S, int* __re
 // Placement of one tile's particles (one workgroup per tile) from the
 // scatter's copy back into the particle arrays.  Pass 1 gives every particle
 // its class and its rank among the particles of its (cell, class), from LDS
-// counters; class and cell are those of the position estimated half a sort
-// interval ahead, x_d + clamp(u_d, -1, 1) hdx_d (|u_d| for the speed below
-// c, its bound above), rounded step by step in double so that a host can
-// restate it exactly, or the present ones when that cell leaves the tile.  Within a class the particles are ranked by (k, r): r is the
+// counters; class and cell are those of the placement key the scatter
+// recorded (placement_key: the position estimated half a sort interval
+// ahead).  Within a class the particles are ranked by (k, r): r is the
 // residue of the particle's cell, k the number of the class's particles of
 // the same residue before it (cells in cell order, a cell's particles in
 // rank order).  The class cycles through the residues it holds, so any RES
@@ -392,70 +444,23 @@ __global__ void __launch_bounds__(PLACE_NT) k_sort_place(SortArrays<R> A, SortPa
   for (int i = threadIdx.x; i <= RES; i += PLACE_NT) ord[TILE_CELLS_MAX + i] = order[TILE_CELLS_MAX + i];
   for (int i = threadIdx.x; i < NC * TILE_CELLS_MAX; i += PLACE_NT) cnt[i] = 0;
   __syncthreads();
-  const int tx = t % S.ntile[0], ty = (t / S.ntile[0]) % S.ntile[1], tz = t / (S.ntile[0] * S.ntile[1]);
-  // pass 1: class and rank of every particle (batches of PB1 per thread,
-  // all loads of a batch in flight together); scratch = rank, class, cell
+  // pass 1: rank of every particle among those of its (class, cell), from
+  // the placement keys the scatter recorded (batches of PB1 per thread, all
+  // loads of a batch in flight together); scratch = rank, class, cell
   constexpr int PB1 = 4;
   for (int i0 = beg + threadIdx.x; i0 < end; i0 += PB1 * PLACE_NT) {
-    int pc[PB1];
-    R po[PB1][3], pu[PB1][3];
+    int kv[PB1];
 #pragma unroll
     for (int k = 0; k < PB1; ++k) {
       const int i = i0 + k * PLACE_NT;
-      pc[k] = 0;
-      po[k][0] = po[k][1] = po[k][2] = R(0);
-      pu[k][0] = pu[k][1] = pu[k][2] = R(0);
-      if (i < end) {
-        pc[k] = A.t_cell[i];
-#pragma unroll
-        for (int d = 0; d < 3; ++d)
-          if (d < dims) {
-            po[k][d] = A.t_off[d][i];
-            pu[k][d] = A.t_u[d][i];
-          }
-      }
+      kv[k] = i < end ? scratch[i] : 0;
     }
 #pragma unroll
     for (int k = 0; k < PB1; ++k) {
       const int i = i0 + k * PLACE_NT;
       if (i < end) {
-        const int cl = pc[k];
-        const uint32_t rest = S.dn0.div((uint32_t)cl);
-        const int cx = cl - (int)rest * S.n[0];
-        int cy = (int)rest, cz = 0;
-        if (dims == 3) {
-          const uint32_t r2 = S.dn1.div(rest);
-          cy = (int)(rest - r2 * S.n[1]);
-          cz = (int)r2;
-        }
-        const int lc[3] = {cx - tx * S.T[0], cy - ty * S.T[1], cz - tz * S.T[2]};
-        int lp[3] = {lc[0], lc[1], lc[2]};
-        double op[3] = {0.0, 0.0, 0.0};
-        bool in = true;
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-          if (d < dims) {
-            const double v = fmin(fmax((double)pu[k][d], -1.0), 1.0);
-            const double x = __dadd_rn((double)po[k][d], __dmul_rn(v, S.hdx[d]));
-            const double f = floor(x);
-            lp[d] = lc[d] + (int)f;
-            op[d] = x - f;
-            in = in && lp[d] >= 0 && lp[d] < S.T[d];
-          }
-        }
-        if (!in) {
-#pragma unroll
-          for (int d = 0; d < 3; ++d) {
-            lp[d] = lc[d];
-            op[d] = (double)po[k][d];
-          }
-        }
-        const int cell = lp[0] + S.T[0] * (lp[1] + S.T[1] * lp[2]);
-        int cls = (op[0] >= 0.5 ? 1 : 0) | (op[1] >= 0.5 ? 2 : 0);
-        if (dims == 3) cls |= op[2] >= 0.5 ? 4 : 0;
-        const int key = cls * TILE_CELLS_MAX + cell;
-        const int rank = atomicAdd(&cnt[key], 1);
-        scratch[i] = (rank << 12) | key;
+        const int rank = atomicAdd(&cnt[kv[k]], 1);
+        scratch[i] = (rank << 12) | kv[k];
       }
     }
   }
@@ -711,10 +716,11 @@ static int launch_sort_t(const pic_ctx* ctx, const pic_particles* p, void* ws, h
   A.id = p->id;
   A.t_cell = (int*)(w + L.tmp_cell);
   A.t_id = (int*)(w + L.tmp_id);
-  k_sort_scatter<R><<<dim3(grid), dim3(256), 0, s>>>(A, np, ncell, c.dims, keys, counts, flg);
+  int* pkey = (int*)(w + L.pkey);
+  k_sort_scatter<R><<<dim3(grid), dim3(256), 0, s>>>(A, S, np, ncell, keys, counts, pkey, flg);
   int* order = (int*)(w + L.order);
   k_sort_order<<<dim3(1), dim3(ORDER_NT), 0, s>>>(S, order);
-  k_sort_place<R><<<dim3((unsigned)S.ntiles), dim3(PLACE_NT), 0, s>>>(A, S, starts, order, keys, c.dims);
+  k_sort_place<R><<<dim3((unsigned)S.ntiles), dim3(PLACE_NT), 0, s>>>(A, S, starts, order, pkey, c.dims);
   // absorbed particles (the dead bin) are not copied back: the caller lowers
   // np to the live count, starts[ntiles]
   return (int)hipGetLastError();

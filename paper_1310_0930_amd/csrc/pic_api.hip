@@ -52,6 +52,8 @@ WsLayout ws_layout(const pic_ctx* ctx, int64_t np) {
   off = align256(off + sizeof(int) * n);
   L.keys = off;
   off = align256(off + sizeof(int) * n);
+  L.pkey = off;
+  off = align256(off + sizeof(int) * n);
   L.order = off;
   off = align256(off + sizeof(int) * 1024);
   L.tmp_real = off;

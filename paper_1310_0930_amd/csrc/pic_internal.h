@@ -176,7 +176,8 @@ struct WsLayout {
   size_t bsum;       // int32[nbins / 1024 + 1]  scan block sums
   size_t rb_tv;      // int32[ntiles]       re-binned pass: slot of each destination tile
   size_t rb_nl;      // int32[ntiles]       re-binned pass: destination tiles
-  size_t keys;       // int32[np]           tile of each particle, then its in-tile bin and cell
+  size_t keys;       // int32[np]           tile of each particle (count, scatter)
+  size_t pkey;       // int32[np]           in-tile placement key of each copied particle, then its rank
   size_t order;      // int32[1024]         a tile's cells listed by bank residue
   size_t tmp_cell;   // int32[np]
   size_t tmp_real;   // R[np * 7]  off[3], u[3], q
